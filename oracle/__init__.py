@@ -1,0 +1,10 @@
+"""FP64 CPU oracle of the shear 4PCF multipole estimator.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py``; never by the library.
+"""
+from .estimator import (NCORR, FACTORS, TABLE1, family_orders, squared_edges,
+                        centre_neighbours, bin_counts, centre_multipoles,
+                        multipoles, contract, upsilon, upsilon_parallel)
+from .brute import brute_upsilon, brute_angular_bins
+from .natural import angular_integrals, binned_from_multipoles, natural_components
