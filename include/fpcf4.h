@@ -1,0 +1,213 @@
+/*
+ * fpcf4.h -- C ABI of libfpcf4, an MI355X (gfx950) implementation of the
+ * multipole-based estimator of the shear four-point correlation function
+ * (Porth, Silvestre-Rosello, Schneider & Larma 2025, arXiv:2509.07974).
+ *
+ * Problem statement (Sect. 3): N galaxies at flat-sky positions theta_i with
+ * Cartesian complex shears gamma_c,i = g1 + i g2 and weights w_i; radial bins
+ * Theta_b; a largest multipole nmax.  The result is the multipole tensor
+ *
+ *   Upsilon_{mu,(n2,n3)}(T1,T2,T3),  mu = 0..7 (x-projection, Sect. 2.2),
+ *   N_{(n2,n3)}(T1,T2,T3)            (the normalisation, Sect. 3.1),
+ *
+ * for |n2|,|n3| <= nmax, summed over all quadruplets of *distinct* galaxies
+ * (double- and triple-counting corrections of Appendix A.1 subtracted), or
+ * over all index quadruplets when subtract_degenerate == 0.
+ *
+ * Conventions shared by every call:
+ *  - All calls return fpcf4_status (0 = OK, < 0 = error).  No C++ exception
+ *    crosses the ABI.  On error, fpcf4_last_error() returns a message for the
+ *    calling thread.  Invalid arguments are detected before any device work.
+ *  - The caller owns every input and output buffer.  The library owns only
+ *    the device workspace it allocates inside a call (freed before return),
+ *    except in the request API where the caller passes the workspace.
+ *  - Radial bin b is the half-open interval [edges[b], edges[b+1]), decided
+ *    on r^2 = dx*dx + dy*dy (two products and one sum in IEEE binary64, no
+ *    fused multiply-add) against the squared edges edges[b]*edges[b]
+ *    (Sect. 2.3 and 3: the bin selection function).  Pairs closer than
+ *    edges[0] or at least edges[nbins] apart are not counted.
+ *  - Position angles phi_ij = atan2(y_j - y_i, x_j - x_i), counter-clockwise
+ *    from +x (Sect. 2.2).  No periodic wrap.
+ *  - Device pointers are HIP device pointers on the current device; `stream`
+ *    is a hipStream_t (NULL = the library's internal stream).  Calls are
+ *    synchronous: results are complete in the output buffer on return.
+ */
+#ifndef FPCF4_H
+#define FPCF4_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fpcf4_status;
+
+enum {
+  FPCF4_OK = 0,
+  FPCF4_E_INVALID_ARG = -1,   /* bad pointer, size, edge array, non-finite input */
+  FPCF4_E_UNSUPPORTED = -2,   /* nmax or nbins beyond the compiled limits        */
+  FPCF4_E_OUT_OF_MEMORY = -3, /* device allocation failed                         */
+  FPCF4_E_DEVICE = -4,        /* a HIP runtime call or kernel launch failed       */
+  FPCF4_E_BUDGET = -5,        /* caller workspace smaller than fpcf4_plan() says  */
+  FPCF4_E_CANCELLED = -6      /* request cancelled                                */
+};
+
+enum { FPCF4_MEM_HOST = 0, FPCF4_MEM_DEVICE = 1 };
+
+/* Arithmetic of the path.
+ *  FPCF4_FP64       : every stage in binary64.
+ *  FPCF4_MIXED_FP16 : pair multipoles accumulated in binary32 with blocked
+ *                     summation into binary64; contraction on MFMA with
+ *                     fp16 hi/lo split operands and fp32 accumulation per
+ *                     centre chunk; binary64 cross-chunk reduction,
+ *                     degenerate-term subtraction and output.
+ *  FPCF4_MIXED_BF16 : as FP16 with bf16 hi/lo split operands. */
+enum { FPCF4_FP64 = 0, FPCF4_MIXED_FP16 = 1, FPCF4_MIXED_BF16 = 2 };
+
+#define FPCF4_NMAX_SUPPORTED 16   /* largest nmax compiled in              */
+#define FPCF4_NBINS_SUPPORTED 16  /* largest number of radial bins         */
+#define FPCF4_NCORR 9             /* Upsilon_0..7 and N                    */
+
+/* Catalogue: structure of arrays of length n, caller-owned, read-only.
+ * Positions in any flat-sky unit (the edges use the same unit).  All values
+ * must be finite; weights may have any sign. */
+typedef struct {
+  int64_t n;
+  const double *x, *y;    /* positions                                     */
+  const double *g1, *g2;  /* gamma_c = g1 + i g2, in the same x/y frame     */
+  const double *w;        /* weights                                       */
+  int32_t mem;            /* FPCF4_MEM_HOST or FPCF4_MEM_DEVICE             */
+} fpcf4_catalogue;
+
+/* Radial bins: nbins + 1 strictly increasing finite edges, edges[0] > 0.
+ * Host memory. */
+typedef struct {
+  int32_t nbins;
+  const double *edges;
+} fpcf4_bins;
+
+typedef struct {
+  int32_t nmax;                /* 0 <= nmax <= FPCF4_NMAX_SUPPORTED          */
+  int32_t precision;           /* FPCF4_FP64 / FPCF4_MIXED_FP16 / _BF16       */
+  int32_t subtract_degenerate; /* 1 = distinct quadruplets, 0 = raw sums      */
+  int32_t reserved;
+  const int64_t *centers;      /* optional: indices of the galaxies used as
+                                  base point X_0 (in catalogue memory space);
+                                  NULL = all.  Every galaxy stays a neighbour. */
+  int64_t ncenters;
+  int64_t tile_centers;        /* centres per stage tile; 0 = planner choice  */
+  void *stream;                /* hipStream_t or NULL                         */
+} fpcf4_options;
+
+/* Number of complex128 elements of the output tensor:
+ * 9 * nbins^3 * (2 nmax + 1)^2. */
+int64_t fpcf4_output_elems(int32_t nbins, int32_t nmax);
+
+/* Full estimate (Sect. 3.1 multipoles, App. A.1 corrections).
+ * upsilon: caller-owned complex128 array, interleaved (re, im), layout
+ *   [9][nbins][nbins][nbins][2nmax+1][2nmax+1], index 0..7 = Upsilon_mu,
+ *   8 = N; the multipole n2 (n3) is stored at offset n2 + nmax (n3 + nmax).
+ * out_mem: FPCF4_MEM_HOST or FPCF4_MEM_DEVICE for `upsilon`.
+ * N < 1 or no pair in range gives zeros with FPCF4_OK. */
+fpcf4_status estimate_4pcf_multipoles(const fpcf4_catalogue *cat,
+                                      const fpcf4_bins *bins,
+                                      const fpcf4_options *opts,
+                                      double *upsilon, int32_t out_mem);
+
+/* Stage (a) only, for parity checks (Sect. 3.1: the per-centre blocks G_n and
+ * W_n "defined as in P24", read as G_k = sum_j w_j gamma_j e^{+ik phi_ij} and
+ * W_k = sum_j w_j e^{+ik phi_ij} over neighbours j in the bin).
+ * For the centres of opts (or all), in that order, writes
+ *   counts[c][b]  : number of neighbours in bin b (int64, may be NULL),
+ *   G[c][b][k]    : complex128 (re, im), k = -2nmax-3 .. 2nmax-1 (may be NULL),
+ *   W[c][b][k]    : complex128, k = -2nmax .. 2nmax (may be NULL).
+ * All outputs in host memory.  Uses opts->precision for the accumulation.
+ * Without opts->centers every galaxy is reported, in catalogue order; a
+ * device-memory catalogue then needs an explicit centre list. */
+fpcf4_status fpcf4_debug_multipoles(const fpcf4_catalogue *cat,
+                                    const fpcf4_bins *bins,
+                                    const fpcf4_options *opts,
+                                    int64_t *counts, double *G, double *W);
+
+/* Conversion to bin-averaged natural components (Sect. 2.3 and Eq. of the
+ * multipole expansion in Sect. 3.1): for nphi linear angular bins on
+ * [0, 2pi),
+ *   Ubar_mu(T, Phi_a, Phi_b) = (2pi)^-2 sum_n Upsilon_mu,n I_n2(Phi_a) I_n3(Phi_b),
+ *   I_0 = |Delta Phi|, I_m = (e^{i m Phi_up} - e^{i m Phi_low}) / (i m),
+ * and Gamma_mu = Ubar_mu / Nbar (0 where Nbar == 0).
+ * upsilon: host complex128 [9][nb][nb][nb][2nmax+1][2nmax+1] (as produced
+ * above); gamma_out: host complex128 [8][nb][nb][nb][nphi][nphi];
+ * norm_out: host double [nb][nb][nb][nphi][nphi] (Re Nbar), may be NULL.
+ * Computed in binary64 on the device. */
+fpcf4_status fpcf4_to_natural(const double *upsilon, int32_t nbins,
+                              int32_t nmax, int32_t nphi, double *gamma_out,
+                              double *norm_out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Request API for serving: the caller sizes and owns the device workspace
+ * (admission by HBM footprint), then advances the request one centre tile
+ * at a time on the request's stream.  A request never allocates.
+ * ---------------------------------------------------------------------- */
+typedef struct fpcf4_request fpcf4_request;
+
+/* Device bytes of workspace and number of centre tiles that a request with
+ * these inputs needs.  Catalogue pointers are not read (may be NULL); only
+ * cat->n, the bins and the options matter. */
+fpcf4_status fpcf4_plan(const fpcf4_catalogue *cat, const fpcf4_bins *bins,
+                        const fpcf4_options *opts, size_t *device_bytes,
+                        int64_t *ntiles);
+
+/* Bind inputs and a caller workspace (device memory of at least the planned
+ * size, 256-byte aligned).  Uploads the catalogue and builds the cell list
+ * on opts->stream.  The catalogue may be freed once this returns. */
+fpcf4_status fpcf4_request_create(const fpcf4_catalogue *cat,
+                                  const fpcf4_bins *bins,
+                                  const fpcf4_options *opts,
+                                  void *device_workspace, size_t bytes,
+                                  fpcf4_request **req);
+
+/* Enqueue stage (a), stage (b) and the correction sums of one centre tile
+ * (0 <= tile < ntiles, each tile exactly once, any order) on the request's
+ * stream.  Returns without waiting for the GPU. */
+fpcf4_status fpcf4_request_step(fpcf4_request *req, int64_t tile);
+
+/* Apply the degenerate-term subtraction and copy the result (layout as for
+ * estimate_4pcf_multipoles) into `upsilon`; waits for the request's stream.
+ * Fails with FPCF4_E_INVALID_ARG unless every tile has been stepped. */
+fpcf4_status fpcf4_request_finalize(fpcf4_request *req, double *upsilon,
+                                    int32_t out_mem);
+
+/* Release the request handle (not the caller's workspace). NULL is a no-op. */
+void fpcf4_request_destroy(fpcf4_request *req);
+
+/* ------------------------------------------------------------------------
+ * Per-stage timing for measurement.  While enabled, every request step
+ * records hipEvents around stage (a) (pair multipoles), stage (b)
+ * (contraction) and the correction sums on the request's stream, and counts
+ * the ordered (centre, neighbour) pairs that fell in a bin; totals are
+ * accumulated when a request is finalized.  Times in milliseconds.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  double stage_a_ms, stage_b_ms, corr_ms;
+  int64_t stage_a_launches, stage_b_launches, steps, pairs, centres;
+} fpcf4_profile;
+
+/* Enable (on != 0) or disable timing; either call resets the totals. */
+fpcf4_status fpcf4_profile_enable(int32_t on);
+
+/* Copy the accumulated totals into *out. */
+fpcf4_status fpcf4_profile_read(fpcf4_profile *out);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *fpcf4_last_error(void);
+
+/* Library version string. */
+const char *fpcf4_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPCF4_H */

@@ -1,0 +1,217 @@
+"""MI355X-native multipole estimator of the shear four-point correlation
+function (Porth et al. 2025, arXiv:2509.07974, Sect. 3).
+
+Thin Python binding over libfpcf4.so (include/fpcf4.h).  Every step of the
+estimator runs in the library's HIP kernels; this module only marshals
+arguments.  Inputs may be NumPy arrays (host) or CUDA/HIP torch tensors
+(device); PyTorch supplies device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (FP64, MIXED_FP16, MIXED_BF16, MEM_HOST, MEM_DEVICE, NMAX_SUPPORTED,
+                   NBINS_SUPPORTED, Fpcf4Error, check, lib)
+
+__all__ = ["estimate_4pcf_multipoles", "debug_multipoles", "to_natural", "plan", "Request",
+           "profile_enable", "profile_read",
+           "PRECISIONS", "Fpcf4Error", "output_shape", "lib", "version"]
+
+PRECISIONS = {"fp64": FP64, "fp16": MIXED_FP16, "bf16": MIXED_BF16}
+
+
+def version() -> str:
+    return lib().fpcf4_version().decode()
+
+
+def output_shape(nbins: int, nmax: int):
+    nn = 2 * nmax + 1
+    return (9, nbins, nbins, nbins, nn, nn)
+
+
+def _is_torch_device(a) -> bool:
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        return False
+    return isinstance(a, torch.Tensor) and a.is_cuda
+
+
+class _Marshal:
+    """Keeps the arrays behind the raw pointers alive for the call."""
+
+    def __init__(self, x, y, g1, g2, w, edges, nmax, precision, subtract_degenerate,
+                 centers, tile_centers, stream):
+        arrs = (x, y, g1, g2, w)
+        self.device = all(_is_torch_device(a) for a in arrs)
+        self.keep = []
+        if self.device:
+            import torch
+            dev = [a.detach().to(torch.float64).contiguous() for a in arrs]
+            n = dev[0].numel()
+            if any(a.numel() != n for a in dev):
+                raise ValueError("catalogue arrays differ in length")
+            self.keep += dev
+            ptrs = [a.data_ptr() for a in dev]
+            mem = MEM_DEVICE
+            if stream is None:
+                stream = torch.cuda.current_stream(dev[0].device).cuda_stream
+            self.torch_device = dev[0].device
+        else:
+            host = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in arrs]
+            n = host[0].size
+            if any(a.size != n for a in host):
+                raise ValueError("catalogue arrays differ in length")
+            self.keep += host
+            ptrs = [a.ctypes.data for a in host]
+            mem = MEM_HOST
+        self.n = n
+        self.cat = _lib.Catalogue(n, *ptrs, mem)
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.float64))
+        self.keep.append(e)
+        self.nbins = e.size - 1
+        self.bins = _lib.Bins(self.nbins, e.ctypes.data)
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        cptr, nc = None, 0
+        if centers is not None:
+            if self.device:
+                import torch
+                ct = torch.as_tensor(centers, dtype=torch.int64, device=self.torch_device).contiguous()
+                self.keep.append(ct)
+                cptr, nc = ct.data_ptr(), ct.numel()
+            else:
+                ca = np.ascontiguousarray(np.asarray(centers, dtype=np.int64))
+                self.keep.append(ca)
+                cptr, nc = ca.ctypes.data, ca.size
+        self.ncent = nc if centers is not None else n
+        self.nmax = int(nmax)
+        self.opts = _lib.Options(self.nmax, prec, 1 if subtract_degenerate else 0, 0, cptr, nc,
+                                 int(tile_centers), stream)
+
+    def refs(self):
+        return C.byref(self.cat), C.byref(self.bins), C.byref(self.opts)
+
+
+def estimate_4pcf_multipoles(x, y, g1, g2, w, edges, nmax: int, precision="fp64",
+                             subtract_degenerate: bool = True, centers=None,
+                             tile_centers: int = 0, stream=None, out=None):
+    """Upsilon_{mu,(n2,n3)}(T1,T2,T3), mu = 0..7, and N (index 8) as a
+    complex128 array [9, nb, nb, nb, 2nmax+1, 2nmax+1] (NumPy for host inputs,
+    a torch tensor on the inputs' device for device inputs)."""
+    m = _Marshal(x, y, g1, g2, w, edges, nmax, precision, subtract_degenerate, centers,
+                 tile_centers, stream)
+    shape = output_shape(m.nbins, m.nmax)
+    if m.device:
+        import torch
+        res = out if out is not None else torch.empty(shape, dtype=torch.complex128, device=m.torch_device)
+        check(lib().estimate_4pcf_multipoles(*m.refs(), C.c_void_p(res.data_ptr()), MEM_DEVICE))
+        return res
+    res = out if out is not None else np.empty(shape, dtype=np.complex128)
+    check(lib().estimate_4pcf_multipoles(*m.refs(), C.c_void_p(res.ctypes.data), MEM_HOST))
+    return res
+
+
+def debug_multipoles(x, y, g1, g2, w, edges, nmax: int, precision="fp64", centers=None,
+                     tile_centers: int = 0, stream=None):
+    """Stage (a) only: (counts int64 [nc, nb], G complex128 [nc, nb, 4nmax+3]
+    for k = -2nmax-3..2nmax-1, W complex128 [nc, nb, 4nmax+1] for
+    k = -2nmax..2nmax), for the centres in the given order."""
+    m = _Marshal(x, y, g1, g2, w, edges, nmax, precision, True, centers, tile_centers, stream)
+    nc, nb, n = m.ncent, m.nbins, m.nmax
+    counts = np.zeros((nc, nb), dtype=np.int64)
+    G = np.zeros((nc, nb, 4 * n + 3), dtype=np.complex128)
+    W = np.zeros((nc, nb, 4 * n + 1), dtype=np.complex128)
+    check(lib().fpcf4_debug_multipoles(*m.refs(), C.c_void_p(counts.ctypes.data),
+                                       C.c_void_p(G.ctypes.data), C.c_void_p(W.ctypes.data)))
+    return counts, G, W
+
+
+def to_natural(upsilon, nphi: int, stream=None):
+    """(Gamma complex128 [8, nb, nb, nb, nphi, nphi], Nbar float64
+    [nb, nb, nb, nphi, nphi]) from the multipoles (host array)."""
+    u = np.ascontiguousarray(np.asarray(upsilon, dtype=np.complex128))
+    nb = u.shape[1]
+    nmax = (u.shape[-1] - 1) // 2
+    gam = np.empty((8, nb, nb, nb, nphi, nphi), dtype=np.complex128)
+    nrm = np.empty((nb, nb, nb, nphi, nphi), dtype=np.float64)
+    check(lib().fpcf4_to_natural(C.c_void_p(u.ctypes.data), nb, nmax, int(nphi),
+                                 C.c_void_p(gam.ctypes.data), C.c_void_p(nrm.ctypes.data), stream))
+    return gam, nrm
+
+
+def profile_enable(on: bool = True):
+    """Enable per-stage hipEvent timing in the library (resets the totals)."""
+    check(lib().fpcf4_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    p = _lib.Profile()
+    check(lib().fpcf4_profile_read(C.byref(p)))
+    return {k: getattr(p, k) for k, _ in _lib.Profile._fields_}
+
+
+def plan(n: int, edges, nmax: int, precision="fp64", ncenters=None, tile_centers: int = 0):
+    """(device_bytes, ntiles) a request with these sizes needs."""
+    z = np.zeros(1)
+    m = _Marshal(z, z, z, z, z, edges, nmax, precision, True, None, tile_centers, None)
+    m.cat.n = int(n)
+    m.cat.mem = MEM_HOST
+    if ncenters is not None:
+        m.opts.ncenters = int(ncenters)
+        m.opts.centers = C.c_void_p(8)   # only the count is read by the planner
+    nbytes = C.c_size_t(0)
+    ntiles = C.c_int64(0)
+    check(lib().fpcf4_plan(*m.refs(), C.byref(nbytes), C.byref(ntiles)))
+    return int(nbytes.value), int(ntiles.value)
+
+
+class Request:
+    """One estimate advanced tile by tile on its own stream, in a caller-owned
+    device workspace (torch uint8 tensor): the serving building block."""
+
+    def __init__(self, x, y, g1, g2, w, edges, nmax, precision="fp16", subtract_degenerate=True,
+                 centers=None, tile_centers: int = 0, stream=None, workspace=None):
+        import torch
+        self.m = _Marshal(x, y, g1, g2, w, edges, nmax, precision, subtract_degenerate, centers,
+                          tile_centers, stream)
+        nbytes = C.c_size_t(0)
+        ntiles = C.c_int64(0)
+        check(lib().fpcf4_plan(*self.m.refs(), C.byref(nbytes), C.byref(ntiles)))
+        self.bytes = int(nbytes.value)
+        self.ntiles = int(ntiles.value)
+        if workspace is None:
+            workspace = torch.empty(self.bytes, dtype=torch.uint8, device="cuda")
+        if workspace.numel() < self.bytes:
+            raise Fpcf4Error(_lib.E_BUDGET, "workspace too small")
+        self.workspace = workspace
+        self.handle = C.c_void_p()
+        check(lib().fpcf4_request_create(*self.m.refs(), C.c_void_p(workspace.data_ptr()),
+                                         self.bytes, C.byref(self.handle)))
+        self.next_tile = 0
+
+    def step(self, tile=None):
+        t = self.next_tile if tile is None else tile
+        check(lib().fpcf4_request_step(self.handle, t))
+        self.next_tile = t + 1
+        return self.next_tile < self.ntiles
+
+    def finalize(self):
+        shape = output_shape(self.m.nbins, self.m.nmax)
+        res = np.empty(shape, dtype=np.complex128)
+        check(lib().fpcf4_request_finalize(self.handle, C.c_void_p(res.ctypes.data), MEM_HOST))
+        return res
+
+    def close(self):
+        if self.handle:
+            lib().fpcf4_request_destroy(self.handle)
+            self.handle = C.c_void_p()
+        self.workspace = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass

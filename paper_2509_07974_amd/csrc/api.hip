@@ -1,0 +1,614 @@
+// Host side of the C ABI: validation, planning, workspace layout and the
+// request life cycle (create -> step per centre tile -> finalize).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fpcf4_internal.hpp"
+
+namespace fpcf4 {
+hipError_t cells_bbox(const double*, const double*, const double*, const double*, const double*,
+                      int64_t, double*, unsigned*, double*, hipStream_t);
+size_t cells_sort_temp_bytes(int64_t n);
+hipError_t cells_build(const double*, const double*, const double*, const double*, const double*,
+                       int64_t, const Grid&, uint32_t*, uint32_t*, int32_t*, int32_t*, void*, size_t,
+                       double*, double*, double*, double*, double*, int32_t*, int32_t*, hipStream_t);
+hipError_t cells_centre_order(const uint32_t*, int64_t, const Grid&, uint32_t*, uint32_t*, int32_t*,
+                              int32_t*, void*, size_t, hipStream_t);
+hipError_t cells_map_centres(const int64_t*, int64_t, const int32_t*, int32_t*, hipStream_t);
+hipError_t natural_components(const double* ups_dev, int nb, int nmax, int nphi, double* tmp,
+                              double* gamma_dev, double* norm_dev, hipStream_t s);
+}  // namespace fpcf4
+
+using namespace fpcf4;
+
+namespace {
+
+thread_local std::string g_err;
+
+fpcf4_status fail(fpcf4_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? FPCF4_E_OUT_OF_MEMORY : FPCF4_E_DEVICE,  \
+                  "%s failed: %s", #call, hipGetErrorString(e_));                      \
+  } while (0)
+
+constexpr size_t ALIGN = 256;
+inline size_t up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
+
+// Default centre tile: records of one tile stay below this many bytes.
+constexpr size_t kTileRecordBudget = size_t(32) << 30;
+
+struct PlanInfo {
+  int64_t n = 0, ncent = 0, tile = 0, ntiles = 0, ldc = 0;
+  int nb = 0, nmax = 0, precision = 0, subtract = 1;
+  Layout L{};
+  size_t tsize = 8;            // bytes per real in records
+  int64_t ncell_cap = 0;
+  size_t sort_tmp = 0;
+  // persistent buffers
+  size_t o_x, o_y, o_fa, o_fb, o_fw, o_cells, o_centres, o_e2, o_edges, o_counters, o_bbox, o_bad,
+      o_pairs, o_part, o_ups, o_corr, o_xg, o_xw, o_counts, o_aos, o_region;
+  size_t region = 0;           // records of one tile, or create-time temporaries
+  // create-time temporaries inside the region
+  size_t t_raw, t_key_a, t_key_b, t_idx_a, t_idx_b, t_inv, t_sort, t_cent64;
+  size_t total = 0;
+};
+
+fpcf4_status validate_common(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
+                             const fpcf4_options* opts) {
+  if (!cat || !bins || !opts) return fail(FPCF4_E_INVALID_ARG, "null argument");
+  if (cat->n < 0) return fail(FPCF4_E_INVALID_ARG, "catalogue size %lld < 0", (long long)cat->n);
+  if (cat->n >= (int64_t(1) << 31) - 1) return fail(FPCF4_E_UNSUPPORTED, "catalogue larger than 2^31-2");
+  if (cat->mem != FPCF4_MEM_HOST && cat->mem != FPCF4_MEM_DEVICE)
+    return fail(FPCF4_E_INVALID_ARG, "catalogue mem flag %d", cat->mem);
+  if (bins->nbins < 1) return fail(FPCF4_E_INVALID_ARG, "nbins must be >= 1");
+  if (bins->nbins > FPCF4_NBINS_SUPPORTED)
+    return fail(FPCF4_E_UNSUPPORTED, "nbins %d > %d", bins->nbins, FPCF4_NBINS_SUPPORTED);
+  if (!bins->edges) return fail(FPCF4_E_INVALID_ARG, "null edges");
+  for (int b = 0; b <= bins->nbins; ++b)
+    if (!std::isfinite(bins->edges[b])) return fail(FPCF4_E_INVALID_ARG, "non-finite edge %d", b);
+  if (!(bins->edges[0] > 0.0)) return fail(FPCF4_E_INVALID_ARG, "edges[0] must be > 0");
+  for (int b = 0; b < bins->nbins; ++b)
+    if (!(bins->edges[b + 1] > bins->edges[b]))
+      return fail(FPCF4_E_INVALID_ARG, "edges not strictly increasing at %d", b);
+  if (opts->nmax < 0) return fail(FPCF4_E_INVALID_ARG, "nmax < 0");
+  if (opts->nmax > FPCF4_NMAX_SUPPORTED)
+    return fail(FPCF4_E_UNSUPPORTED, "nmax %d > %d", opts->nmax, FPCF4_NMAX_SUPPORTED);
+  if (opts->precision < FPCF4_FP64 || opts->precision > FPCF4_MIXED_BF16)
+    return fail(FPCF4_E_INVALID_ARG, "precision %d", opts->precision);
+  if (opts->centers && opts->ncenters < 0) return fail(FPCF4_E_INVALID_ARG, "ncenters < 0");
+  if (opts->tile_centers < 0) return fail(FPCF4_E_INVALID_ARG, "tile_centers < 0");
+  if (cat->n > 0 && (!cat->x || !cat->y || !cat->g1 || !cat->g2 || !cat->w))
+    return fail(FPCF4_E_INVALID_ARG, "null catalogue array");
+  return FPCF4_OK;
+}
+
+fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
+                       const fpcf4_options* opts, PlanInfo& P) {
+  fpcf4_status st = validate_common(cat, bins, opts);
+  if (st != FPCF4_OK) return st;
+  P.n = cat->n;
+  P.nb = bins->nbins;
+  P.nmax = opts->nmax;
+  P.precision = opts->precision;
+  P.subtract = opts->subtract_degenerate ? 1 : 0;
+  P.ncent = opts->centers ? opts->ncenters : cat->n;
+  P.L = make_layout(P.nmax);
+  P.tsize = (P.precision == FPCF4_FP64) ? 8 : 4;
+  const size_t rec_per_centre = (size_t)P.nb * P.L.mpc * 2 * P.tsize;
+  int64_t tile = opts->tile_centers;
+  if (tile <= 0) tile = (int64_t)(kTileRecordBudget / rec_per_centre);
+  if (tile > P.ncent) tile = P.ncent;
+  if (tile < 1) tile = 1;
+  if (tile > (int64_t(1) << 30)) tile = int64_t(1) << 30;
+  P.tile = tile;
+  P.ldc = (tile + 15) / 16 * 16;
+  P.ntiles = P.ncent > 0 ? (P.ncent + tile - 1) / tile : 0;
+  const int64_t n = P.n > 0 ? P.n : 1;
+  P.ncell_cap = std::max<int64_t>(int64_t(1) << 16, 4 * n);
+  P.sort_tmp = cells_sort_temp_bytes(n);
+  const int nn = 2 * P.nmax + 1;
+
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += up(bytes); return o; };
+  P.o_x = take(n * 8);
+  P.o_y = take(n * 8);
+  P.o_fa = take(n * 8);
+  P.o_fb = take(n * 8);
+  P.o_fw = take(n * 8);
+  P.o_cells = take((P.ncell_cap + 1) * 4);
+  P.o_centres = take((size_t)std::max<int64_t>(P.ncent, 1) * 4);
+  P.o_e2 = take((P.nb + 1) * 8);
+  P.o_edges = take((P.nb + 1) * 8);
+  P.o_counters = take(256 * 4);   // 128 scheduling counters + 64 scaling maxima
+  P.o_bbox = take(4 * 8);
+  P.o_bad = take(16);
+  P.o_pairs = take(16);
+  P.o_part = take(256 * 4 * 8);
+  P.o_ups = take((size_t)9 * P.nb * P.nb * P.nb * nn * nn * 16);
+  P.o_corr = take(corr_elems(P.nb, P.nmax) * 16);
+  P.o_xg = take((size_t)P.ldc * 2 * P.tsize);
+  P.o_xw = take((size_t)P.ldc * P.tsize);
+  P.o_aos = take((size_t)P.tile * rec_per_centre);
+  P.o_counts = take((size_t)P.tile * P.nb * 4);
+  // region: one tile of records, or the create-time temporaries
+  size_t t = 0;
+  auto ttake = [&](size_t bytes) { size_t o = t; t += up(bytes); return o; };
+  P.t_raw = ttake(n * 8 * 5);
+  P.t_key_a = ttake(n * 4);
+  P.t_key_b = ttake(n * 4);
+  P.t_idx_a = ttake(n * 4);
+  P.t_idx_b = ttake(n * 4);
+  P.t_inv = ttake(n * 4);
+  P.t_cent64 = ttake((size_t)std::max<int64_t>(P.ncent, 1) * 8);
+  P.t_sort = ttake(P.sort_tmp);
+  P.region = std::max(t, up((size_t)P.ldc * rec_per_centre));
+  P.o_region = take(P.region);
+  P.total = off;
+  return FPCF4_OK;
+}
+
+std::once_flag g_pool_once;
+void setup_pool() {
+  std::call_once(g_pool_once, [] {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return;
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  });
+}
+
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+fpcf4_profile g_prof{};
+
+__global__ void zero_kernel(int32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
+struct fpcf4_request {
+  PlanInfo P;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Grid grid{};
+  std::vector<char> stepped;
+  bool want_counts = false;
+  std::vector<hipEvent_t> ev;   // 4 per profiled step
+  int64_t prof_a_launches = 0, prof_b_launches = 0, prof_steps = 0, prof_centres = 0;
+  ~fpcf4_request() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  template <typename U> U* at(size_t off) const { return reinterpret_cast<U*>(ws + off); }
+};
+
+namespace {
+
+fpcf4_status request_init(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
+                          const fpcf4_options* opts, void* wsp, size_t bytes, fpcf4_request* R) {
+  PlanInfo& P = R->P;
+  fpcf4_status st = make_plan(cat, bins, opts, P);
+  if (st != FPCF4_OK) return st;
+  if (!wsp) return fail(FPCF4_E_INVALID_ARG, "null workspace");
+  if (reinterpret_cast<uintptr_t>(wsp) % ALIGN) return fail(FPCF4_E_INVALID_ARG, "workspace not 256-byte aligned");
+  if (bytes < P.total) return fail(FPCF4_E_BUDGET, "workspace %zu bytes < planned %zu", bytes, P.total);
+  R->ws = static_cast<char*>(wsp);
+  R->stream = static_cast<hipStream_t>(opts->stream);
+  R->stepped.assign((size_t)P.ntiles, 0);
+  hipStream_t s = R->stream;
+  const int64_t n = P.n;
+  const int nn = 2 * P.nmax + 1;
+
+  // centre subset: validate on the host
+  std::vector<int64_t> hc;
+  if (opts->centers && P.ncent > 0) {
+    hc.resize((size_t)P.ncent);
+    if (cat->mem == FPCF4_MEM_HOST) {
+      std::memcpy(hc.data(), opts->centers, hc.size() * 8);
+    } else {
+      HIPCHK(hipMemcpyAsync(hc.data(), opts->centers, hc.size() * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    for (int64_t k = 0; k < P.ncent; ++k)
+      if (hc[k] < 0 || hc[k] >= n) return fail(FPCF4_E_INVALID_ARG, "centre index %lld out of range", (long long)hc[k]);
+  }
+
+  HIPCHK(hipMemsetAsync(R->ws + P.o_pairs, 0, 16, s));
+  HIPCHK(hipMemsetAsync(R->ws + P.o_ups, 0, (size_t)9 * P.nb * P.nb * P.nb * nn * nn * 16, s));
+  HIPCHK(hipMemsetAsync(R->ws + P.o_corr, 0, corr_elems(P.nb, P.nmax) * 16, s));
+  std::vector<double> e2(P.nb + 1);
+  for (int b = 0; b <= P.nb; ++b) e2[b] = bins->edges[b] * bins->edges[b];
+  HIPCHK(hipMemcpyAsync(R->ws + P.o_e2, e2.data(), e2.size() * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(R->ws + P.o_edges, bins->edges, e2.size() * 8, hipMemcpyHostToDevice, s));
+  if (n == 0) {
+    HIPCHK(hipStreamSynchronize(s));
+    return FPCF4_OK;
+  }
+
+  char* reg = R->ws + P.o_region;
+  const double *x, *y, *g1, *g2, *w;
+  if (cat->mem == FPCF4_MEM_HOST) {
+    double* raw = reinterpret_cast<double*>(reg + P.t_raw);
+    const double* src[5] = {cat->x, cat->y, cat->g1, cat->g2, cat->w};
+    for (int k = 0; k < 5; ++k)
+      HIPCHK(hipMemcpyAsync(raw + k * n, src[k], n * 8, hipMemcpyHostToDevice, s));
+    x = raw; y = raw + n; g1 = raw + 2 * n; g2 = raw + 3 * n; w = raw + 4 * n;
+  } else {
+    x = cat->x; y = cat->y; g1 = cat->g1; g2 = cat->g2; w = cat->w;
+  }
+  unsigned* bad = R->at<unsigned>(P.o_bad);
+  HIPCHK(hipMemsetAsync(bad, 0, 16, s));
+  HIPCHK(cells_bbox(x, y, g1, g2, w, n, R->at<double>(P.o_part), bad, R->at<double>(P.o_bbox), s));
+  double bb[4];
+  unsigned hbad = 0;
+  HIPCHK(hipMemcpyAsync(bb, R->ws + P.o_bbox, 32, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hbad) return fail(FPCF4_E_INVALID_ARG, "catalogue has %u non-finite entries", hbad);
+
+  // cell grid: side ~ outer edge / 24 (<= ~51 cell rows per annulus), capped cell count
+  const double rmax = bins->edges[P.nb];
+  double h = rmax / 24.0;
+  const double wx = bb[1] - bb[0], wy = bb[3] - bb[2];
+  for (;;) {
+    const double ncx = std::floor(wx / h) + 1.0, ncy = std::floor(wy / h) + 1.0;
+    if (ncx * ncy <= (double)P.ncell_cap) break;
+    h *= 1.25;
+  }
+  Grid& g = R->grid;
+  g.x0 = bb[0];
+  g.y0 = bb[2];
+  g.h = h;
+  g.inv_h = 1.0 / h;
+  g.ncx = (int)(std::floor(wx / h) + 1.0);
+  g.ncy = (int)(std::floor(wy / h) + 1.0);
+
+  uint32_t* key_a = reinterpret_cast<uint32_t*>(reg + P.t_key_a);
+  uint32_t* key_b = reinterpret_cast<uint32_t*>(reg + P.t_key_b);
+  int32_t* idx_a = reinterpret_cast<int32_t*>(reg + P.t_idx_a);
+  int32_t* idx_b = reinterpret_cast<int32_t*>(reg + P.t_idx_b);
+  int32_t* inv = reinterpret_cast<int32_t*>(reg + P.t_inv);
+  void* sort_tmp = reg + P.t_sort;
+  HIPCHK(cells_build(x, y, g1, g2, w, n, g, key_a, key_b, idx_a, idx_b, sort_tmp, P.sort_tmp,
+                     R->at<double>(P.o_x), R->at<double>(P.o_y), R->at<double>(P.o_fa),
+                     R->at<double>(P.o_fb), R->at<double>(P.o_fw), R->at<int32_t>(P.o_cells), inv, s));
+  int32_t* centres = R->at<int32_t>(P.o_centres);
+  if (opts->centers) {
+    if (P.ncent > 0) {
+      int64_t* c64 = reinterpret_cast<int64_t*>(reg + P.t_cent64);
+      HIPCHK(hipMemcpyAsync(c64, hc.data(), hc.size() * 8, hipMemcpyHostToDevice, s));
+      HIPCHK(cells_map_centres(c64, P.ncent, inv, centres, s));
+    }
+  } else {
+    // key_a / idx_a are free again after the sort; reuse them for the Morton sort
+    HIPCHK(cells_centre_order(key_b, n, g, key_a, reinterpret_cast<uint32_t*>(inv), idx_a, centres,
+                              sort_tmp, P.sort_tmp, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return FPCF4_OK;
+}
+
+fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
+  PlanInfo& P = R->P;
+  if (tile < 0 || tile >= P.ntiles) return fail(FPCF4_E_INVALID_ARG, "tile %lld out of range", (long long)tile);
+  if (R->stepped[(size_t)tile]) return fail(FPCF4_E_INVALID_ARG, "tile %lld already stepped", (long long)tile);
+  hipStream_t s = R->stream;
+  const int64_t c0 = tile * P.tile;
+  const int ncent = (int)std::min<int64_t>(P.tile, P.ncent - c0);
+  int32_t* counters = R->at<int32_t>(P.o_counters);
+  bool prof;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof = g_prof_on && stage_b;
+  }
+  hipEvent_t evs[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (prof) {
+    for (auto& e : evs) HIPCHK(hipEventCreate(&e));
+    for (auto e : evs) R->ev.push_back(e);
+    HIPCHK(hipEventRecord(evs[0], s));
+  }
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(256), 0, s, counters, 256);
+  HIPCHK(hipGetLastError());
+  StageAArgs a{};
+  a.cat.n = P.n;
+  a.cat.x = R->at<double>(P.o_x);
+  a.cat.y = R->at<double>(P.o_y);
+  a.cat.fa = R->at<double>(P.o_fa);
+  a.cat.fb = R->at<double>(P.o_fb);
+  a.cat.fw = R->at<double>(P.o_fw);
+  a.cat.cell_start = R->at<int32_t>(P.o_cells);
+  a.cat.g = R->grid;
+  a.centres = R->at<int32_t>(P.o_centres) + c0;
+  a.ncent = ncent;
+  a.nb = P.nb;
+  a.ldc = (int32_t)P.ldc;
+  a.xg = R->ws + P.o_xg;
+  a.xw = R->ws + P.o_xw;
+  a.maxima = P.precision == FPCF4_FP64 ? nullptr : reinterpret_cast<unsigned*>(counters + 128);
+  a.e2 = R->at<double>(P.o_e2);
+  a.edges = R->at<double>(P.o_edges);
+  a.rec = R->ws + P.o_region;
+  a.rec_aos = R->ws + P.o_aos;
+  a.counts = R->want_counts ? R->at<int32_t>(P.o_counts) : nullptr;
+  a.work_counter = counters;
+  a.pairs = R->at<unsigned long long>(P.o_pairs);
+  int npass = 0;
+  if (P.precision == FPCF4_FP64) HIPCHK(launch_stage_a<double>(P.nmax, a, s, &npass));
+  else HIPCHK(launch_stage_a<float>(P.nmax, a, s, &npass));
+  if (prof) HIPCHK(hipEventRecord(evs[1], s));
+  if (stage_b) {
+    StageBArgs b{};
+    b.rec = a.rec;
+    b.centres = a.centres;
+    b.fa = a.cat.fa;
+    b.fb = a.cat.fb;
+    b.fw = a.cat.fw;
+    b.ncent = ncent;
+    b.nb = P.nb;
+    b.nmax = P.nmax;
+    b.ups = R->at<double>(P.o_ups);
+    b.corr = R->at<double>(P.o_corr);
+    HIPCHK(launch_contract(b, P.precision, (int)P.ldc, a.xg, a.xw, a.maxima, s));
+    if (prof) HIPCHK(hipEventRecord(evs[2], s));
+    CorrArgs ca{a.rec, a.xg, a.xw, ncent, P.nb, P.nmax, (int32_t)P.ldc, b.corr};
+    if (P.precision == FPCF4_FP64) HIPCHK(launch_corrections<double>(ca, s));
+    else HIPCHK(launch_corrections<float>(ca, s));
+    if (prof) {
+      HIPCHK(hipEventRecord(evs[3], s));
+      R->prof_a_launches += npass;
+      R->prof_b_launches += 7;
+      R->prof_steps += 1;
+      R->prof_centres += ncent;
+    }
+  }
+  R->stepped[(size_t)tile] = 1;
+  return FPCF4_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t fpcf4_output_elems(int32_t nbins, int32_t nmax) {
+  if (nbins < 0 || nmax < 0) return 0;
+  const int64_t nn = 2 * (int64_t)nmax + 1;
+  return 9 * (int64_t)nbins * nbins * nbins * nn * nn;
+}
+
+const char* fpcf4_last_error(void) { return g_err.c_str(); }
+const char* fpcf4_version(void) { return "fpcf4 0.1 (gfx950)"; }
+
+fpcf4_status fpcf4_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins, const fpcf4_options* opts,
+                        size_t* device_bytes, int64_t* ntiles) {
+  PlanInfo P;
+  fpcf4_status st = make_plan(cat, bins, opts, P);
+  if (st != FPCF4_OK) return st;
+  if (device_bytes) *device_bytes = P.total;
+  if (ntiles) *ntiles = P.ntiles;
+  return FPCF4_OK;
+}
+
+fpcf4_status fpcf4_request_create(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
+                                  const fpcf4_options* opts, void* ws, size_t bytes,
+                                  fpcf4_request** req) {
+  if (!req) return fail(FPCF4_E_INVALID_ARG, "null request pointer");
+  *req = nullptr;
+  fpcf4_request* R = new (std::nothrow) fpcf4_request();
+  if (!R) return fail(FPCF4_E_OUT_OF_MEMORY, "host allocation failed");
+  fpcf4_status st = request_init(cat, bins, opts, ws, bytes, R);
+  if (st != FPCF4_OK) {
+    delete R;
+    return st;
+  }
+  *req = R;
+  return FPCF4_OK;
+}
+
+fpcf4_status fpcf4_request_step(fpcf4_request* req, int64_t tile) {
+  if (!req) return fail(FPCF4_E_INVALID_ARG, "null request");
+  return request_step(req, tile, true);
+}
+
+fpcf4_status fpcf4_request_finalize(fpcf4_request* req, double* upsilon, int32_t out_mem) {
+  if (!req || !upsilon) return fail(FPCF4_E_INVALID_ARG, "null argument");
+  if (out_mem != FPCF4_MEM_HOST && out_mem != FPCF4_MEM_DEVICE) return fail(FPCF4_E_INVALID_ARG, "out_mem %d", out_mem);
+  PlanInfo& P = req->P;
+  for (size_t t = 0; t < req->stepped.size(); ++t)
+    if (!req->stepped[t]) return fail(FPCF4_E_INVALID_ARG, "tile %zu not stepped", t);
+  hipStream_t s = req->stream;
+  double* ups = req->at<double>(P.o_ups);
+  HIPCHK(launch_finalize(ups, req->at<double>(P.o_corr), P.nb, P.nmax, P.subtract, ups, s));
+  const size_t bytes = (size_t)fpcf4_output_elems(P.nb, P.nmax) * 16;
+  HIPCHK(hipMemcpyAsync(upsilon, ups, bytes,
+                        out_mem == FPCF4_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (!req->ev.empty()) {
+    unsigned long long pairs = 0;
+    HIPCHK(hipMemcpy(&pairs, req->ws + P.o_pairs, 8, hipMemcpyDeviceToHost));
+    double ta = 0, tb = 0, tc = 0;
+    for (size_t k = 0; k + 3 < req->ev.size(); k += 4) {
+      float x = 0;
+      HIPCHK(hipEventElapsedTime(&x, req->ev[k], req->ev[k + 1]));
+      ta += x;
+      HIPCHK(hipEventElapsedTime(&x, req->ev[k + 1], req->ev[k + 2]));
+      tb += x;
+      HIPCHK(hipEventElapsedTime(&x, req->ev[k + 2], req->ev[k + 3]));
+      tc += x;
+    }
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.stage_a_ms += ta;
+    g_prof.stage_b_ms += tb;
+    g_prof.corr_ms += tc;
+    g_prof.stage_a_launches += req->prof_a_launches;
+    g_prof.stage_b_launches += req->prof_b_launches;
+    g_prof.steps += req->prof_steps;
+    g_prof.pairs += (int64_t)pairs;
+    g_prof.centres += req->prof_centres;
+  }
+  return FPCF4_OK;
+}
+
+void fpcf4_request_destroy(fpcf4_request* req) { delete req; }
+
+fpcf4_status fpcf4_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  g_prof = fpcf4_profile{};
+  return FPCF4_OK;
+}
+
+fpcf4_status fpcf4_profile_read(fpcf4_profile* out) {
+  if (!out) return fail(FPCF4_E_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  *out = g_prof;
+  return FPCF4_OK;
+}
+
+fpcf4_status estimate_4pcf_multipoles(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
+                                      const fpcf4_options* opts, double* upsilon, int32_t out_mem) {
+  if (!upsilon) return fail(FPCF4_E_INVALID_ARG, "null output");
+  PlanInfo P;
+  fpcf4_status st = make_plan(cat, bins, opts, P);
+  if (st != FPCF4_OK) return st;
+  setup_pool();
+  hipStream_t s = static_cast<hipStream_t>(opts->stream);
+  void* ws = nullptr;
+  HIPCHK(hipMallocAsync(&ws, P.total, s));
+  fpcf4_request* R = nullptr;
+  st = fpcf4_request_create(cat, bins, opts, ws, P.total, &R);
+  for (int64_t t = 0; st == FPCF4_OK && t < P.ntiles; ++t) st = fpcf4_request_step(R, t);
+  if (st == FPCF4_OK) st = fpcf4_request_finalize(R, upsilon, out_mem);
+  fpcf4_request_destroy(R);
+  hipError_t e = hipFreeAsync(ws, s);
+  if (st == FPCF4_OK && e != hipSuccess) return fail(FPCF4_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));
+  return st;
+}
+
+fpcf4_status fpcf4_debug_multipoles(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
+                                    const fpcf4_options* opts_in, int64_t* counts, double* G, double* W) {
+  if (!cat || !bins || !opts_in) return fail(FPCF4_E_INVALID_ARG, "null argument");
+  // without a subset, report every galaxy in catalogue order
+  fpcf4_options o = *opts_in;
+  std::vector<int64_t> all;
+  fpcf4_catalogue c = *cat;
+  if (!o.centers && cat->n > 0) {
+    if (cat->mem == FPCF4_MEM_DEVICE) {
+      // the subset array lives in the catalogue's memory space; use a host copy
+      return fail(FPCF4_E_INVALID_ARG, "debug on a device catalogue needs an explicit centre list");
+    }
+    all.resize((size_t)cat->n);
+    for (int64_t i = 0; i < cat->n; ++i) all[(size_t)i] = i;
+    o.centers = all.data();
+    o.ncenters = cat->n;
+  }
+  const fpcf4_options* opts = &o;
+  cat = &c;
+  PlanInfo P;
+  fpcf4_status st = make_plan(cat, bins, opts, P);
+  if (st != FPCF4_OK) return st;
+  setup_pool();
+  hipStream_t s = static_cast<hipStream_t>(opts->stream);
+  void* ws = nullptr;
+  HIPCHK(hipMallocAsync(&ws, P.total, s));
+  fpcf4_request* R = new fpcf4_request();
+  R->want_counts = true;
+  st = request_init(cat, bins, opts, ws, P.total, R);
+  const Layout& L = R->P.L;
+  const int nb = P.nb, n = P.nmax;
+  std::vector<int32_t> hcnt;
+  std::vector<char> hrec;
+  for (int64_t t = 0; st == FPCF4_OK && t < P.ntiles; ++t) {
+    st = request_step(R, t, false);
+    if (st != FPCF4_OK) break;
+    const int64_t c0 = t * P.tile;
+    const int64_t nc = std::min<int64_t>(P.tile, P.ncent - c0);
+    hcnt.resize((size_t)(nc * nb));
+    hrec.resize((size_t)(L.mpc * nb * P.ldc * 2 * P.tsize));
+    hipError_t e = hipMemcpyAsync(hcnt.data(), R->ws + P.o_counts, hcnt.size() * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hrec.data(), R->ws + P.o_region, hrec.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { st = fail(FPCF4_E_DEVICE, "debug copy: %s", hipGetErrorString(e)); break; }
+    for (int64_t c = 0; c < nc; ++c) {
+      for (int b = 0; b < nb; ++b) {
+        const int64_t cb = c * nb + b, gcb = (c0 + c) * nb + b;
+        if (counts) counts[gcb] = hcnt[(size_t)cb];
+        auto val = [&](int e, int part) -> double {
+          const size_t o = (((size_t)e * nb + b) * P.ldc + c) * 2 + part;
+          if (P.tsize == 8) return reinterpret_cast<const double*>(hrec.data())[o];
+          return (double)reinterpret_cast<const float*>(hrec.data())[o];
+        };
+        if (G)
+          for (int k = 0; k < 4 * n + 3; ++k) {
+            G[(gcb * (4 * n + 3) + k) * 2] = val(L.offG + k, 0);
+            G[(gcb * (4 * n + 3) + k) * 2 + 1] = val(L.offG + k, 1);
+          }
+        if (W)
+          for (int k = 0; k < 4 * n + 1; ++k) {
+            W[(gcb * (4 * n + 1) + k) * 2] = val(L.offW + k, 0);
+            W[(gcb * (4 * n + 1) + k) * 2 + 1] = val(L.offW + k, 1);
+          }
+      }
+    }
+  }
+  delete R;
+  hipError_t e = hipFreeAsync(ws, s);
+  if (st == FPCF4_OK && e != hipSuccess) return fail(FPCF4_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));
+  if (st == FPCF4_OK) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(FPCF4_E_DEVICE, "sync: %s", hipGetErrorString(e));
+  }
+  return st;
+}
+
+fpcf4_status fpcf4_to_natural(const double* upsilon, int32_t nbins, int32_t nmax, int32_t nphi,
+                              double* gamma_out, double* norm_out, void* stream) {
+  if (!upsilon || !gamma_out) return fail(FPCF4_E_INVALID_ARG, "null argument");
+  if (nbins < 1 || nbins > FPCF4_NBINS_SUPPORTED) return fail(FPCF4_E_INVALID_ARG, "nbins %d", nbins);
+  if (nmax < 0 || nmax > FPCF4_NMAX_SUPPORTED) return fail(FPCF4_E_INVALID_ARG, "nmax %d", nmax);
+  if (nphi < 1 || nphi > 4096) return fail(FPCF4_E_INVALID_ARG, "nphi %d", nphi);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  setup_pool();
+  const int64_t nb3 = (int64_t)nbins * nbins * nbins, nn = 2 * nmax + 1;
+  const size_t in_b = (size_t)(9 * nb3 * nn * nn) * 16;
+  const size_t tmp_b = (size_t)(9 * nb3 * nphi * nn) * 16;
+  const size_t g_b = (size_t)(8 * nb3 * nphi * nphi) * 16;
+  const size_t n_b = (size_t)(nb3 * nphi * nphi) * 8;
+  char* buf = nullptr;
+  HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&buf), up(in_b) + up(tmp_b) + up(g_b) + up(n_b), s));
+  double* din = reinterpret_cast<double*>(buf);
+  double* dtmp = reinterpret_cast<double*>(buf + up(in_b));
+  double* dg = reinterpret_cast<double*>(buf + up(in_b) + up(tmp_b));
+  double* dn = reinterpret_cast<double*>(buf + up(in_b) + up(tmp_b) + up(g_b));
+  fpcf4_status st = FPCF4_OK;
+  hipError_t e = hipMemcpyAsync(din, upsilon, in_b, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = natural_components(din, nbins, nmax, nphi, dtmp, dg, dn, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(gamma_out, dg, g_b, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && norm_out) e = hipMemcpyAsync(norm_out, dn, n_b, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) st = fail(FPCF4_E_DEVICE, "to_natural: %s", hipGetErrorString(e));
+  (void)hipFreeAsync(buf, s);
+  (void)hipStreamSynchronize(s);
+  return st;
+}
+
+}  // extern "C"

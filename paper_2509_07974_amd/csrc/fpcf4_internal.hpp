@@ -1,0 +1,138 @@
+// Internal declarations of libfpcf4 (host and device).
+//
+// Per-centre multipole record.  For every centre and radial bin, stage (a)
+// writes one record of complex entries (binary64 in the FP64 path, binary32
+// in the mixed paths).  The entries are the blocks the contraction and the
+// degenerate-term subtraction read (Sect. 3.1, App. A.1 Table 1):
+//
+//   G_k = sum_j w_j gamma_j e^{ik phi_ij}       k = -2n-3 .. 2n-1
+//   W_k = sum_j w_j e^{ik phi_ij}               k = -2n   .. 2n
+//   Q_k = sum_j (w_j gamma_j)^2 e^{ik phi_ij}   k = qlo   .. qhi
+//   A_k = sum_j |w_j gamma_j|^2 e^{ik phi_ij}   k = 0 .. ka  (A_-k = conj A_k)
+//   V_k = sum_j w_j^2 e^{ik phi_ij}             k = 0 .. 2n  (V_-k = conj V_k)
+//   T_-8, T_-4 with T_k = sum_j (w_j gamma_j)^3 e^{ik phi_ij}
+//   M_-4, M_0  with M_k = sum_j |w_j gamma_j|^2 w_j gamma_j e^{ik phi_ij}
+//   U = sum_j w_j^3
+//
+// with qlo = min(-2n-5, -n-6), qhi = max(2n-3, n-2), ka = max(2n+1, n+2):
+// exactly the orders the factor table of Sect. 3.1 and Table 1 touch for
+// |n2|, |n3| <= n.  Records are laid out [entry][bin][centre] (centre
+// contiguous, row stride ldc), so the contraction and the correction sums
+// stream centres with coalesced loads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/fpcf4.h"
+
+namespace fpcf4 {
+
+struct Layout {
+  int n;                // nmax
+  int qlo, qhi, ka;     // Q order range, A top order
+  int offG, offW, offQ, offA, offV, offS;
+  int mpc;              // complex entries used
+  int rec;              // complex entries per record (even)
+};
+
+__host__ __device__ constexpr int imax(int a, int b) { return a > b ? a : b; }
+__host__ __device__ constexpr int imin(int a, int b) { return a < b ? a : b; }
+
+__host__ __device__ inline Layout make_layout(int n) {
+  Layout L{};
+  L.n = n;
+  L.qlo = imin(-2 * n - 5, -n - 6);
+  L.qhi = imax(2 * n - 3, n - 2);
+  L.ka = imax(2 * n + 1, n + 2);
+  L.offG = 0;
+  L.offW = L.offG + 4 * n + 3;
+  L.offQ = L.offW + 4 * n + 1;
+  L.offA = L.offQ + (L.qhi - L.qlo + 1);
+  L.offV = L.offA + L.ka + 1;
+  L.offS = L.offV + 2 * n + 1;
+  L.mpc = L.offS + 5;
+  L.rec = (L.mpc + 1) & ~1;
+  return L;
+}
+
+// entry indices inside a record
+__host__ __device__ inline int eG(const Layout& L, int k) { return L.offG + k + 2 * L.n + 3; }
+__host__ __device__ inline int eW(const Layout& L, int k) { return L.offW + k + 2 * L.n; }
+__host__ __device__ inline int eQ(const Layout& L, int k) { return L.offQ + k - L.qlo; }
+__host__ __device__ inline int eA(const Layout& L, int k) { return L.offA + k; }
+__host__ __device__ inline int eV(const Layout& L, int k) { return L.offV + k; }
+enum { S_T8 = 0, S_T4 = 1, S_M4 = 2, S_M0 = 3, S_U = 4 };
+
+// Cell grid of the spatially sorted catalogue (row-major cells).
+struct Grid {
+  double x0, y0, h, inv_h;
+  int ncx, ncy;
+};
+
+// Sorted structure-of-arrays catalogue on the device.
+struct SortedCat {
+  int64_t n;
+  const double* x;
+  const double* y;
+  const double* fa;   // w g1
+  const double* fb;   // w g2
+  const double* fw;   // w
+  const int32_t* cell_start;  // [ncx*ncy + 1]
+  Grid g;
+};
+
+struct StageAArgs {
+  SortedCat cat;
+  const int32_t* centres;   // sorted positions of this tile's centres
+  int32_t ncent;
+  int32_t nb;
+  int32_t ldc;              // centre stride of record rows (>= ncent, multiple of 16)
+  const double* e2;         // device squared edges [nb+1]
+  const double* edges;      // device edges [nb+1]
+  void* rec;                // records [entry][bin][ldc] complex (T)
+  void* rec_aos;            // staging [centre][bin][entry] complex (T)
+  void* xg;                 // [ldc] complex (T): w g of each tile centre
+  void* xw;                 // [ldc] (T): w of each tile centre
+  unsigned* maxima;         // fp16 scaling maxima (float bits) or null
+  int32_t* counts;          // [ncent][nb] or null
+  int32_t* work_counter;    // dynamic centre scheduling counters [8 per pass]
+  unsigned long long* pairs;  // in-bin pair counter (may be null)
+};
+
+// stage (a) launcher, T = double or float; returns the number of kernel
+// launches (passes) in *npass
+template <typename T> hipError_t launch_stage_a(int nmax, const StageAArgs& a, hipStream_t s, int* npass);
+
+struct StageBArgs {
+  const void* rec;          // records of the tile
+  const int32_t* centres;   // sorted positions of the tile's centres
+  const double* fa;
+  const double* fb;
+  const double* fw;
+  int32_t ncent;
+  int32_t nb;
+  int32_t nmax;
+  double* ups;              // [9][nb][nb][nb][nn][nn] complex128 accumulator
+  double* corr;             // correction sums (see stage_b.hip)
+};
+
+struct CorrArgs {
+  const void* rec;
+  const void* xg;
+  const void* xw;
+  int32_t ncent, nb, nmax, ldc;
+  double* corr;
+};
+
+// contraction on MFMA (precision: FPCF4_FP64 / _MIXED_FP16 / _MIXED_BF16)
+hipError_t launch_contract(const StageBArgs& sb, int precision, int ldc, const void* xg,
+                           const void* xw, const unsigned* maxima, hipStream_t s);
+template <typename T> hipError_t launch_corrections(const CorrArgs& a, hipStream_t s);
+size_t corr_elems(int nb, int nmax);  // complex elements of the correction buffer
+hipError_t launch_finalize(const double* ups_raw, const double* corr, int nb, int nmax,
+                           int subtract, double* out, hipStream_t s);
+
+}  // namespace fpcf4

@@ -1,0 +1,583 @@
+// Stage (b) on the matrix cores: contraction of three per-centre blocks into
+// the 4PCF multipoles (Sect. 3.1)
+//
+//   Upsilon_mu[b1,b2,b3; n2,n3] = sum_i X[i,b1] Y[i,b2] Z[i,b3],
+//   X = x_i A^mu(b1, n2+n3),  Y = B^mu(b2, n2),  Z = C^mu(b3, n3).
+//
+// For fixed (mu, n2, n3) this is a GEMM over the centre index i:
+//   Out[(mu, b2), (b1, b3)] = sum_i Y[i, b2] * R[i, (b1, b3)],  R = X (x) Z,
+// i.e. Y is the left operand and the Khatri-Rao product R (formed on the
+// fly) the right one.  Correlators that share (x, A, C) share R and are
+// stacked as extra rows (mu 0 and 3; mu 1 and 6), so 7 formations serve 9
+// correlators.  Complex arithmetic is split into real MFMAs:
+//   [Out_r; Out_i] = [[Y_r, -Y_i], [Y_i, Y_r]] [R_r; R_i]
+// (rows: (mu, re/im, b2); columns: (b1, b3) packed densely; K: (centre,
+// re/im)).
+//
+// Mixed precision (FP16 / BF16): every operand v is split v = hi + lo with
+// hi, lo in the 16-bit format and v_mfma_f32_16x16x32_{f16,bf16} forms
+// hi*hi + hi*lo + lo*hi with fp32 accumulation.  Operands are pre-scaled by
+// per-bin powers of two (from the tile's maxima) so the fp16 range is never
+// exceeded; the scale is undone exactly.  The fp32 accumulators are folded
+// into binary64 registers every 512 centres and the binary64 sums are added
+// to the output in a fixed order (deterministic, no atomics).
+//
+// Binary64: the same GEMM with v_mfma_f64_16x16x4_f64, no split, no scale.
+//
+// Work decomposition: one workgroup of 4 waves per (correlator group, n2,
+// n3); the waves share the LDS-staged chunk of 32 centres (X, Z, and the
+// split Y operand) and take disjoint (b1, b3) column tiles.  The global loads
+// of chunk k+1 are issued into registers before the MFMAs of chunk k and
+// committed to the other LDS buffer after them.
+#include "factors.hpp"
+#include "fpcf4_internal.hpp"
+
+namespace fpcf4 {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bh8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+struct Group {
+  int nmu;
+  int mu[2];
+};
+__host__ __device__ constexpr Group group_of(int g) {
+  return g == 0 ? Group{2, {0, 3}}
+       : g == 1 ? Group{2, {1, 6}}
+       : g == 2 ? Group{1, {2, 2}}
+       : g == 3 ? Group{1, {4, 4}}
+       : g == 4 ? Group{1, {5, 5}}
+       : g == 5 ? Group{1, {7, 7}}
+                : Group{1, {8, 8}};
+}
+constexpr int NGROUPS = 7;
+__host__ __device__ constexpr bool same_fac(const Fac& a, const Fac& b) {
+  return a.fam == b.fam && a.conj == b.conj && a.a == b.a && a.b == b.b && a.c == b.c;
+}
+// correlators stacked in a group must share the centre factor, A and C
+static_assert(mu_factors(0).x == mu_factors(3).x && same_fac(mu_factors(0).A, mu_factors(3).A) &&
+                  same_fac(mu_factors(0).C, mu_factors(3).C),
+              "mu 0/3 must share x, A, C");
+static_assert(mu_factors(1).x == mu_factors(6).x && same_fac(mu_factors(1).A, mu_factors(6).A) &&
+                  same_fac(mu_factors(1).C, mu_factors(6).C),
+              "mu 1/6 must share x, A, C");
+
+constexpr int KC = 32;       // centres per LDS chunk (two fp16 MFMA K-steps)
+
+// row tiles (16 rows of (mu, re/im, b2)) and column tiles per wave (16
+// columns of (b1, b3), 4 waves) for a bin-count class NBC in {8, 12, 16}
+__host__ __device__ constexpr int mt_of(int nmu, int nbc) { return (nmu * 2 * nbc + 15) / 16; }
+__host__ __device__ constexpr int ntw_of(int nbc) { return ((nbc * nbc + 15) / 16 + 3) / 4; }
+
+__device__ __forceinline__ int fac_entry_k(const Layout& L, const Fac& f, int k) {
+  return f.fam == F_G ? eG(L, k) : eW(L, k);
+}
+
+template <typename T>
+struct C2 {
+  T r, i;
+};
+
+template <typename T>
+__device__ __forceinline__ C2<T> ldrec(const T* rec, int64_t row, int64_t ldc, int c) {
+  const T* p = rec + 2 * (row * ldc + c);
+  return {p[0], p[1]};
+}
+
+// maxima used for the fp16 scaling (set by stage (a)): [0..15] G per bin,
+// [16..31] W per bin, [32] |x| for w g, [33] w; stored as float bits.
+__device__ __forceinline__ float pow2_below(float m, int target_exp) {
+  if (!(m > 0.0f)) return 1.0f;
+  int e;
+  frexpf(m, &e);                  // m < 2^e
+  return ldexpf(1.0f, target_exp - e);
+}
+
+template <int PREC>
+struct Half8;
+template <>
+struct Half8<FPCF4_MIXED_FP16> {
+  typedef h8 type;
+};
+template <>
+struct Half8<FPCF4_MIXED_BF16> {
+  typedef bh8 type;
+};
+
+template <int PREC>
+__device__ __forceinline__ void split8v(const float (&v)[8], typename Half8<PREC>::type& hi,
+                                        typename Half8<PREC>::type& lo) {
+  if constexpr (PREC == FPCF4_MIXED_FP16) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const _Float16 h = (_Float16)v[q];
+      hi[q] = h;
+      lo[q] = (_Float16)(v[q] - (float)h);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const __bf16 h = (__bf16)v[q];
+      hi[q] = h;
+      lo[q] = (__bf16)(v[q] - (float)h);
+    }
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ f4 mfma16(const typename Half8<PREC>::type& a,
+                                     const typename Half8<PREC>::type& b, f4 c) {
+  if constexpr (PREC == FPCF4_MIXED_FP16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+struct BArgs {
+  StageBArgs s;
+  int ldc;                 // centre stride of the record rows
+  const void* xg;          // per tile centre: complex (w g) in record precision
+  const void* xw;          // per tile centre: w
+  const unsigned* maxima;  // scaling maxima (mixed only)
+};
+
+// Values a thread stages for one chunk: X and Z for two (bin, centre) slots
+// and the Y column of up to two (row tile, lane) slots, held in registers
+// across the compute of the previous chunk (software pipelining).
+template <typename T>
+struct Prefetch {
+  C2<T> xc[2], av[2], cv[2];
+  C2<T> y[2][4];
+};
+
+// ---------------------------------------------------------------------------
+// mixed precision
+// ---------------------------------------------------------------------------
+template <int PREC, int G, int NBC>
+__global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
+  typedef typename Half8<PREC>::type H8;
+  constexpr Group GR = group_of(G);
+  constexpr MuFactors F0 = mu_factors(GR.mu[0]);
+  constexpr MuFactors F1 = mu_factors(GR.mu[1]);
+  constexpr int MT = mt_of(GR.nmu, NBC);
+  constexpr int NTW = ntw_of(NBC);
+  constexpr int KS = KC / 16;          // fp16 K-steps (16 centres) per chunk
+  const int nb = a.s.nb, n = a.s.nmax, nn = 2 * n + 1;
+  const Layout L = make_layout(n);
+  const int n2 = (int)blockIdx.x / nn - n;
+  const int n3 = (int)blockIdx.x % nn - n;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int mrows = GR.nmu * 2 * nb;
+  const int mt = (mrows + 15) >> 4;
+  const int ncols = nb * nb;
+  const int ntiles = (ncols + 15) >> 4;
+  const int ncent = a.s.ncent;
+  const float* rec = reinterpret_cast<const float*>(a.s.rec);
+  const int ldc = a.ldc;
+
+  const int rowA = fac_entry_k(L, F0.A, F0.A.a * n2 + F0.A.b * n3 + F0.A.c);
+  const int rowC = fac_entry_k(L, F0.C, F0.C.b * n3 + F0.C.c);
+  const int rowB0 = fac_entry_k(L, F0.B, F0.B.a * n2 + F0.B.c);
+  const int rowB1 = fac_entry_k(L, F1.B, F1.B.a * n2 + F1.B.c);
+  constexpr int famA = F0.A.fam == F_G ? 0 : 16;
+  constexpr int famB = F0.B.fam == F_G ? 0 : 16;
+  constexpr int famC = F0.C.fam == F_G ? 0 : 16;
+
+  __shared__ C2<float> Xs[2][16][KC];
+  __shared__ C2<float> Zs[2][16][KC];
+  __shared__ H8 Ys[2][KS][MT][2][64];   // split Y operand in MFMA lane order
+  __shared__ float sc_lds[3][16];       // scales of X (per b1), Y (b2), Z (b3)
+
+  if (tid < 16) {
+    const unsigned* M = a.maxima;
+    const float mx = __uint_as_float(M[F0.x == X_W ? 33 : 32]);
+    // |X| = |x A| <= 2 max|x| max|A|, |Z| <= 1.5 max|C| (component maxima);
+    // X and Z below 2^6 keep |X Z| below 2^12, Y below 2^14 (fp16 max 65504)
+    float sx = 1.0f, sy = 1.0f, sz = 1.0f;
+    if (tid < nb) {
+      sx = pow2_below(2.0f * mx * __uint_as_float(M[famA + tid]), 6);
+      sy = pow2_below(__uint_as_float(M[famB + tid]), 14);
+      sz = pow2_below(1.5f * __uint_as_float(M[famC + tid]), 6);
+    }
+    sc_lds[0][tid] = sx;
+    sc_lds[1][tid] = sy;
+    sc_lds[2][tid] = sz;
+  }
+
+  // ---- staging: global -> registers (issue), registers -> LDS (commit)
+  const C2<float>* xg = reinterpret_cast<const C2<float>*>(a.xg);
+  const float* xw = reinterpret_cast<const float*>(a.xw);
+  Prefetch<float> pf;
+  auto issue = [&](int c0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int slot = tid + 256 * h;          // (bin, centre) slot of X and Z
+      const int b = slot / KC, cc = slot % KC, c = c0 + cc;
+      pf.xc[h] = {0.f, 0.f};
+      pf.av[h] = {0.f, 0.f};
+      pf.cv[h] = {0.f, 0.f};
+      if (b < nb && c < ncent) {
+        if (F0.x == X_W) pf.xc[h] = {xw[c], 0.f};
+        else pf.xc[h] = xg[c];
+        pf.av[h] = ldrec(rec, (int64_t)rowA * nb + b, ldc, c);
+        pf.cv[h] = ldrec(rec, (int64_t)rowC * nb + b, ldc, c);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = tid + 256 * h;             // (K-step, row tile, lane) slot of Y
+      const int ks = q / (MT * 64), m = (q / 64) % MT, l = q & 63;
+      const int r = 16 * m + (l & 15);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pf.y[h][u] = {0.f, 0.f};
+      if (ks < KS && r < mrows) {
+        const int mi = r / (2 * nb), b2 = r % nb;
+        const int rowB = mi ? rowB1 : rowB0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = c0 + 16 * ks + 4 * (l >> 4) + u;
+          if (c < ncent) pf.y[h][u] = ldrec(rec, (int64_t)rowB * nb + b2, ldc, c);
+        }
+      }
+    }
+  };
+  auto commit = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int slot = tid + 256 * h;
+      const int b = slot / KC, cc = slot % KC;
+      if (b < nb) {
+        C2<float> xc = pf.xc[h], av = pf.av[h], cv = pf.cv[h];
+        if (F0.x == X_GC) xc.i = -xc.i;
+        if (F0.A.conj) av.i = -av.i;
+        if (F0.C.conj) cv.i = -cv.i;
+        const float sx = sc_lds[0][b], sz = sc_lds[2][b];
+        Xs[buf][b][cc] = {(xc.r * av.r - xc.i * av.i) * sx, (xc.r * av.i + xc.i * av.r) * sx};
+        Zs[buf][b][cc] = {cv.r * sz, cv.i * sz};
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = tid + 256 * h;
+      const int ks = q / (MT * 64), m = (q / 64) % MT, l = q & 63;
+      if (ks >= KS) continue;
+      const int r = 16 * m + (l & 15);
+      float v[8];
+      if (r < mrows) {
+        const int mi = r / (2 * nb), part = (r % (2 * nb)) / nb, b2 = r % nb;
+        const int cjB = mi ? F1.B.conj : F0.B.conj;
+        const float sy = sc_lds[1][b2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          C2<float> y = pf.y[h][u];
+          if (cjB) y.i = -y.i;
+          // row part 0 (real out): [ y_r, -y_i ];  part 1 (imag out): [ y_i, y_r ]
+          v[2 * u] = (part ? y.i : y.r) * sy;
+          v[2 * u + 1] = (part ? y.r : -y.i) * sy;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = 0.f;
+      }
+      H8 hi, lo;
+      split8v<PREC>(v, hi, lo);
+      Ys[buf][ks][m][0][l] = hi;
+      Ys[buf][ks][m][1][l] = lo;
+    }
+  };
+
+  // per-lane column (b1, b3) of each of this wave's tiles
+  int b1c[NTW], b3c[NTW];
+  bool colok[NTW], tok[NTW];
+#pragma unroll
+  for (int t = 0; t < NTW; ++t) {
+    const int T = wv + 4 * t;
+    const int j = 16 * T + (lane & 15);
+    tok[t] = T < ntiles;
+    colok[t] = tok[t] && (j < ncols);
+    b1c[t] = colok[t] ? j / nb : 0;
+    b3c[t] = colok[t] ? j % nb : 0;
+  }
+
+  f4 acc[MT][NTW];
+  double acc64[MT][NTW][4];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+      acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[m][t][r] = 0.0;
+    }
+
+  const int nchunks = (ncent + KC - 1) / KC;
+  __syncthreads();              // scales visible
+  issue(0);
+  commit(0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nchunks;
+    if (more) issue((ch + 1) * KC);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      H8 yh[MT], yl[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        yh[m] = Ys[buf][ks][m][0][lane];
+        yl[m] = Ys[buf][ks][m][1][lane];
+      }
+      const int cb = 16 * ks + 4 * (lane >> 4);
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        if (!tok[t]) continue;
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const C2<float> xv = Xs[buf][b1c[t]][cb + u];
+          const C2<float> zv = Zs[buf][b3c[t]][cb + u];
+          v[2 * u] = colok[t] ? xv.r * zv.r - xv.i * zv.i : 0.f;
+          v[2 * u + 1] = colok[t] ? xv.r * zv.i + xv.i * zv.r : 0.f;
+        }
+        H8 rh, rl;
+        split8v<PREC>(v, rh, rl);
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+          if (m < mt) {
+            acc[m][t] = mfma16<PREC>(yh[m], rh, acc[m][t]);
+            acc[m][t] = mfma16<PREC>(yh[m], rl, acc[m][t]);
+            acc[m][t] = mfma16<PREC>(yl[m], rh, acc[m][t]);
+          }
+      }
+    }
+    if ((ch & 15) == 15 || !more) {       // fold fp32 into binary64 every 512 centres
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[m][t][r] += (double)acc[m][t][r];
+          acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    if (more) commit(buf ^ 1);
+    __syncthreads();
+  }
+
+  // write: D row = 4*(lane/16) + r in tile m, column = lane%16 in tile t
+#pragma unroll
+  for (int t = 0; t < NTW; ++t) {
+    if (!colok[t]) continue;
+    const int b1 = b1c[t], b3 = b3c[t];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      if (m >= mt) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * m + 4 * (lane >> 4) + r;
+        if (row >= mrows) continue;
+        const int mi = row / (2 * nb), rem = row % (2 * nb), part = rem / nb, b2 = rem % nb;
+        const int mu = mi ? GR.mu[1] : GR.mu[0];
+        const double unscale = 1.0 / ((double)sc_lds[0][b1] * sc_lds[1][b2] * sc_lds[2][b3]);
+        const int64_t o = (((((int64_t)mu * nb + b1) * nb + b2) * nb + b3) * nn + (n2 + n)) * nn + (n3 + n);
+        a.s.ups[2 * o + part] += acc64[m][t][r] * unscale;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// binary64
+// ---------------------------------------------------------------------------
+template <int G, int NBC>
+__global__ __launch_bounds__(256) void contract_f64_kernel(BArgs a) {
+  constexpr Group GR = group_of(G);
+  constexpr MuFactors F0 = mu_factors(GR.mu[0]);
+  constexpr MuFactors F1 = mu_factors(GR.mu[1]);
+  constexpr int MT = mt_of(GR.nmu, NBC);
+  constexpr int NTW = ntw_of(NBC);
+  const int nb = a.s.nb, n = a.s.nmax, nn = 2 * n + 1;
+  const Layout L = make_layout(n);
+  const int n2 = (int)blockIdx.x / nn - n;
+  const int n3 = (int)blockIdx.x % nn - n;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int mrows = GR.nmu * 2 * nb;
+  const int mt = (mrows + 15) >> 4;
+  const int ncols = nb * nb;
+  const int ntiles = (ncols + 15) >> 4;
+  const int ncent = a.s.ncent;
+  const double* rec = reinterpret_cast<const double*>(a.s.rec);
+  const int ldc = a.ldc;
+  const int rowA = fac_entry_k(L, F0.A, F0.A.a * n2 + F0.A.b * n3 + F0.A.c);
+  const int rowC = fac_entry_k(L, F0.C, F0.C.b * n3 + F0.C.c);
+  const int rowB0 = fac_entry_k(L, F0.B, F0.B.a * n2 + F0.B.c);
+  const int rowB1 = fac_entry_k(L, F1.B, F1.B.a * n2 + F1.B.c);
+
+  __shared__ C2<double> Xs[2][16][KC];
+  __shared__ C2<double> Zs[2][16][KC];
+  __shared__ C2<double> Ys[2][GR.nmu][16][KC];   // [mu idx][b2][centre]
+
+  const C2<double>* xg = reinterpret_cast<const C2<double>*>(a.xg);
+  const double* xw = reinterpret_cast<const double*>(a.xw);
+  struct PF {
+    C2<double> xc, av, cv, y0, y1;
+  } pf[2];
+  auto issue = [&](int c0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int slot = tid + 256 * h;
+      const int b = slot / KC, cc = slot % KC, c = c0 + cc;
+      pf[h].xc = pf[h].av = pf[h].cv = pf[h].y0 = pf[h].y1 = {0.0, 0.0};
+      if (b < nb && c < ncent) {
+        if (F0.x == X_W) pf[h].xc = {xw[c], 0.0};
+        else pf[h].xc = xg[c];
+        pf[h].av = ldrec(rec, (int64_t)rowA * nb + b, ldc, c);
+        pf[h].cv = ldrec(rec, (int64_t)rowC * nb + b, ldc, c);
+        pf[h].y0 = ldrec(rec, (int64_t)rowB0 * nb + b, ldc, c);
+        if (GR.nmu == 2) pf[h].y1 = ldrec(rec, (int64_t)rowB1 * nb + b, ldc, c);
+      }
+    }
+  };
+  auto commit = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int slot = tid + 256 * h;
+      const int b = slot / KC, cc = slot % KC;
+      if (b < nb) {
+        C2<double> xc = pf[h].xc, av = pf[h].av, cv = pf[h].cv, y0 = pf[h].y0, y1 = pf[h].y1;
+        if (F0.x == X_GC) xc.i = -xc.i;
+        if (F0.A.conj) av.i = -av.i;
+        if (F0.C.conj) cv.i = -cv.i;
+        if (F0.B.conj) y0.i = -y0.i;
+        if (F1.B.conj) y1.i = -y1.i;
+        Xs[buf][b][cc] = {xc.r * av.r - xc.i * av.i, xc.r * av.i + xc.i * av.r};
+        Zs[buf][b][cc] = cv;
+        Ys[buf][0][b][cc] = y0;
+        if (GR.nmu == 2) Ys[buf][GR.nmu - 1][b][cc] = y1;
+      }
+    }
+  };
+
+  int arow_mi[MT], arow_part[MT], arow_b2[MT];
+  bool arow_ok[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int r = 16 * m + (lane & 15);
+    arow_ok[m] = r < mrows;
+    const int rr = arow_ok[m] ? r : 0;
+    arow_mi[m] = rr / (2 * nb);
+    arow_part[m] = (rr % (2 * nb)) / nb;
+    arow_b2[m] = rr % nb;
+  }
+  int b1c[NTW], b3c[NTW];
+  bool colok[NTW], tok[NTW];
+#pragma unroll
+  for (int t = 0; t < NTW; ++t) {
+    const int T = wv + 4 * t;
+    const int j = 16 * T + (lane & 15);
+    tok[t] = T < ntiles;
+    colok[t] = tok[t] && (j < ncols);
+    b1c[t] = colok[t] ? j / nb : 0;
+    b3c[t] = colok[t] ? j % nb : 0;
+  }
+  d4 acc[MT][NTW];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) acc[m][t] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int nchunks = (ncent + KC - 1) / KC;
+  const int kq = lane >> 4;  // k within the K=4 step: (centre = kq/2, part = kq%2)
+  issue(0);
+  commit(0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nchunks;
+    if (more) issue((ch + 1) * KC);
+#pragma unroll 4
+    for (int ks = 0; ks < KC / 2; ++ks) {
+      const int cc = 2 * ks + (kq >> 1);
+      const int pk = kq & 1;
+      double av[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const C2<double> y = Ys[buf][arow_mi[m]][arow_b2[m]][cc];
+        // [[y_r, -y_i], [y_i, y_r]]
+        const double v = arow_part[m] ? (pk ? y.r : y.i) : (pk ? -y.i : y.r);
+        av[m] = arow_ok[m] ? v : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        if (!tok[t]) continue;
+        const C2<double> xv = Xs[buf][b1c[t]][cc];
+        const C2<double> zv = Zs[buf][b3c[t]][cc];
+        double bv = pk ? xv.r * zv.i + xv.i * zv.r : xv.r * zv.r - xv.i * zv.i;
+        bv = colok[t] ? bv : 0.0;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+          if (m < mt) acc[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv, acc[m][t], 0, 0, 0);
+      }
+    }
+    if (more) commit(buf ^ 1);
+    __syncthreads();
+  }
+
+  // f64 D layout: element r of lane L is row 4 r + L/16, column L%16
+#pragma unroll
+  for (int t = 0; t < NTW; ++t) {
+    if (!colok[t]) continue;
+    const int b1 = b1c[t], b3 = b3c[t];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      if (m >= mt) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * m + 4 * r + (lane >> 4);
+        if (row >= mrows) continue;
+        const int mi = row / (2 * nb), rem = row % (2 * nb), part = rem / nb, b2 = rem % nb;
+        const int mu = mi ? GR.mu[1] : GR.mu[0];
+        const int64_t o = (((((int64_t)mu * nb + b1) * nb + b2) * nb + b3) * nn + (n2 + n)) * nn + (n3 + n);
+        a.s.ups[2 * o + part] += acc[m][t][r];
+      }
+    }
+  }
+}
+
+template <int G, int NBC>
+static void launch_group_nbc(const BArgs& a, int precision, hipStream_t s) {
+  const int nn = 2 * a.s.nmax + 1;
+  const dim3 grid(nn * nn);
+  if (precision == FPCF4_FP64)
+    hipLaunchKernelGGL((contract_f64_kernel<G, NBC>), grid, dim3(256), 0, s, a);
+  else if (precision == FPCF4_MIXED_FP16)
+    hipLaunchKernelGGL((contract_mixed_kernel<FPCF4_MIXED_FP16, G, NBC>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((contract_mixed_kernel<FPCF4_MIXED_BF16, G, NBC>), grid, dim3(256), 0, s, a);
+}
+
+template <int G>
+static hipError_t launch_group(const BArgs& a, int precision, hipStream_t s) {
+  if (a.s.nb <= 8) launch_group_nbc<G, 8>(a, precision, s);
+  else if (a.s.nb <= 12) launch_group_nbc<G, 12>(a, precision, s);
+  else launch_group_nbc<G, 16>(a, precision, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_contract(const StageBArgs& sb, int precision, int ldc, const void* xg,
+                           const void* xw, const unsigned* maxima, hipStream_t s) {
+  if (sb.ncent <= 0) return hipSuccess;
+  BArgs a{sb, ldc, xg, xw, maxima};
+  hipError_t e;
+  if ((e = launch_group<0>(a, precision, s)) != hipSuccess) return e;
+  if ((e = launch_group<1>(a, precision, s)) != hipSuccess) return e;
+  if ((e = launch_group<2>(a, precision, s)) != hipSuccess) return e;
+  if ((e = launch_group<3>(a, precision, s)) != hipSuccess) return e;
+  if ((e = launch_group<4>(a, precision, s)) != hipSuccess) return e;
+  if ((e = launch_group<5>(a, precision, s)) != hipSuccess) return e;
+  return launch_group<6>(a, precision, s);
+}
+
+}  // namespace fpcf4

@@ -1,0 +1,76 @@
+"""C-ABI library: loads, exports every declared symbol, rejects invalid
+arguments before touching a device (runs without a GPU)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from helpers import ensure_built, header_functions
+
+
+def test_header_declares_expected_api():
+    names = header_functions()
+    for n in ["estimate_4pcf_multipoles", "fpcf4_debug_multipoles", "fpcf4_to_natural",
+              "fpcf4_plan", "fpcf4_request_create", "fpcf4_request_step",
+              "fpcf4_request_finalize", "fpcf4_request_destroy", "fpcf4_last_error"]:
+        assert n in names
+
+
+def test_library_exports_all_header_symbols():
+    lib = ensure_built()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_output_elems():
+    lib = ensure_built()
+    assert b"gfx950" in lib.fpcf4_version()
+    assert lib.fpcf4_output_elems(4, 3) == 9 * 64 * 49
+    assert lib.fpcf4_output_elems(12, 10) == 9 * 1728 * 441
+
+
+def _call(edges, nmax=2, n=10, precision=0, xs=None):
+    from paper_2509_07974_amd import _lib
+    ensure_built()
+    rng = np.random.default_rng(0)
+    arrs = [rng.uniform(0, 10, n) for _ in range(5)] if xs is None else xs
+    cat = _lib.Catalogue(n, *[a.ctypes.data for a in arrs], _lib.MEM_HOST)
+    e = np.asarray(edges, dtype=np.float64)
+    bins = _lib.Bins(e.size - 1, e.ctypes.data)
+    opts = _lib.Options(nmax, precision, 1, 0, None, 0, 0, None)
+    out = np.zeros(max(1, 9 * (e.size - 1) ** 3 * (2 * max(nmax, 0) + 1) ** 2), complex)
+    st = _lib.lib().estimate_4pcf_multipoles(C.byref(cat), C.byref(bins), C.byref(opts),
+                                             C.c_void_p(out.ctypes.data), _lib.MEM_HOST)
+    return st, _lib.lib().fpcf4_last_error().decode()
+
+
+@pytest.mark.parametrize("edges,nmax,code", [
+    ([1.0, 0.5, 2.0], 2, -1),          # not increasing
+    ([0.0, 1.0, 2.0], 2, -1),          # edges[0] <= 0
+    ([-1.0, 1.0], 2, -1),
+    ([1.0, np.nan, 3.0], 2, -1),       # non-finite edge
+    ([1.0, 2.0], -1, -1),              # nmax < 0
+    ([1.0, 2.0], 17, -2),              # beyond compiled nmax
+    (list(np.geomspace(1, 10, 18)), 2, -2),   # 17 bins > 16
+    ([1.0], 2, -1),                    # no bin
+])
+def test_invalid_arguments_rejected(edges, nmax, code):
+    st, msg = _call(edges, nmax)
+    assert st == code and msg
+
+
+def test_bad_precision_and_null_output():
+    from paper_2509_07974_amd import _lib
+    st, _ = _call([1.0, 2.0], 2, precision=7)
+    assert st == _lib.E_INVALID_ARG
+    lib = ensure_built()
+    st = lib.estimate_4pcf_multipoles(None, None, None, None, 0)
+    assert st == _lib.E_INVALID_ARG
+
+
+def test_python_binding_rejects_mismatched_lengths():
+    import paper_2509_07974_amd as m
+    ensure_built()
+    with pytest.raises(ValueError):
+        m.estimate_4pcf_multipoles(np.zeros(3), np.zeros(4), np.zeros(3), np.zeros(3), np.zeros(3),
+                                   [1.0, 2.0], 1)

@@ -1,0 +1,182 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: neighbour/bin counts bit-exact; stage (a) multipoles <= 1e-12 (FP64)
+and <= 1e-6 (binary32 accumulation); Upsilon <= 1e-10 normwise per
+correlator in the FP64 path and <= 1e-5 in the mixed paths.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import maxabs_per_mu, rel_per_mu
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp16": 1e-5, "bf16": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import paper_2509_07974_amd as m
+    m.lib()
+    return m
+
+
+@functools.lru_cache(None)
+def c0():
+    cat, edges, nmax, _ = synth.workload("uniform-2k")
+    return cat, edges, nmax
+
+
+@functools.lru_cache(None)
+def c0_ref(distinct=True):
+    cat, edges, nmax = c0()
+    return oracle.upsilon(*cat.arrays(), edges, nmax, distinct=distinct)
+
+
+def test_c0_counts_bit_exact(fp):
+    cat, edges, nmax = c0()
+    for prec in ("fp64", "fp16"):
+        counts, _, _ = fp.debug_multipoles(*cat.arrays(), edges, nmax, precision=prec)
+        ref = oracle.bin_counts(cat.x, cat.y, edges, range(cat.n))
+        assert np.array_equal(counts, ref), prec
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp16", 1e-6)])
+def test_c0_stage_a_multipoles(fp, prec, tol):
+    cat, edges, nmax = c0()
+    idx = np.arange(0, cat.n, 7)
+    _, G, W = fp.debug_multipoles(*cat.arrays(), edges, nmax, precision=prec, centers=idx)
+    mp = oracle.multipoles(*cat.arrays(), edges, nmax, idx)
+    lo, hi = mp["ranges"]["G"]
+    assert (lo, hi) == (-2 * nmax - 3, 2 * nmax - 1)
+    eg = np.linalg.norm(G - mp["G"]) / np.linalg.norm(mp["G"])
+    ew = np.linalg.norm(W - mp["W"]) / np.linalg.norm(mp["W"])
+    assert eg < tol and ew < tol, (eg, ew)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16", "bf16"])
+def test_c0_upsilon_distinct(fp, prec):
+    cat, edges, nmax = c0()
+    got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision=prec)
+    ref = c0_ref(True)
+    err = rel_per_mu(got, ref)
+    print(prec, "normwise", err, "maxabs", maxabs_per_mu(got, ref))
+    assert np.all(err < TOL[prec]), err
+
+
+def test_c0_upsilon_raw_fp64(fp):
+    cat, edges, nmax = c0()
+    got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp64",
+                                      subtract_degenerate=False)
+    err = rel_per_mu(got, c0_ref(False))
+    assert np.all(err < 1e-10), err
+
+
+def test_tiles_with_ragged_tail_match_single_tile(fp):
+    cat, edges, nmax = c0()
+    one = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp64")
+    many = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp64", tile_centers=333)
+    assert np.all(rel_per_mu(many, one) < 1e-13)
+
+
+def test_centre_subset(fp):
+    cat, edges, nmax = c0()
+    idx = np.random.default_rng(5).choice(cat.n, 97, replace=False)
+    for prec in ("fp64", "fp16"):
+        got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision=prec, centers=idx)
+        ref = oracle.upsilon(*cat.arrays(), edges, nmax, centers=idx)
+        assert np.all(rel_per_mu(got, ref) < TOL[prec])
+
+
+def test_degenerate_inputs(fp):
+    edges = np.array([1.0, 2.0, 4.0])
+    z = np.zeros(0)
+    out = fp.estimate_4pcf_multipoles(z, z, z, z, z, edges, 2)
+    assert out.shape == (9, 2, 2, 2, 5, 5) and not np.any(out)
+    # three galaxies: only raw terms, distinct quadruplets impossible
+    x = np.array([0.0, 1.5, 0.0]); y = np.array([0.0, 0.0, 3.0])
+    g = np.array([0.1, -0.2, 0.05]); w = np.array([1.0, 2.0, 0.5])
+    got = fp.estimate_4pcf_multipoles(x, y, g, g[::-1].copy(), w, edges, 2, subtract_degenerate=False)
+    ref = oracle.upsilon(x, y, g, g[::-1].copy(), w, edges, 2, distinct=False)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-15)
+    got = fp.estimate_4pcf_multipoles(x, y, g, g[::-1].copy(), w, edges, 2)
+    assert np.abs(got).max() < 1e-14
+    # no pair in range
+    x = np.arange(5) * 100.0
+    got = fp.estimate_4pcf_multipoles(x, x, x * 0, x * 0, x * 0 + 1, edges, 2)
+    assert not np.any(got)
+
+
+def test_hand_example_on_gpu(fp):
+    # same configuration as the oracle's hand example (tests/test_oracle.py)
+    x = np.array([0.0, 1.5, 0.0, -7.0]); y = np.array([0.0, 0.0, 3.0, 0.0])
+    g1 = np.array([0.0, 0.0, 0.0, -0.1]); g2 = np.array([0.1, 0.2, 0.3, 0.0])
+    w = np.array([2.0, 1.0, 1.0, 1.0]); edges = np.array([1.0, 2.0, 4.0, 8.0])
+    got = fp.estimate_4pcf_multipoles(x, y, g1, g2, w, edges, 2, centers=[0])
+    P = [0.0012j, -0.0012j, -0.0012j, -0.0012j, 0.0012j, 0.0012j, 0.0012j, -0.0012j, 2.0]
+    for mu in range(9):
+        for (n2, n3), ph in {(0, 0): 1, (1, 0): -1j, (0, 1): -1, (1, 1): 1j, (-1, 2): 1j}.items():
+            assert abs(got[mu, 0, 1, 2, n2 + 2, n3 + 2] - P[mu] * ph) < 1e-15
+
+
+def test_device_inputs_match_host(fp):
+    import torch
+    cat, edges, nmax = c0()
+    host = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp64")
+    dev = [torch.from_numpy(a).cuda() for a in cat.arrays()]
+    got = fp.estimate_4pcf_multipoles(*dev, edges, nmax, precision="fp64")
+    torch.cuda.synchronize()
+    assert np.all(rel_per_mu(got.cpu().numpy(), host) < 1e-14)
+
+
+def test_invariances_on_gpu(fp):
+    cat, edges, nmax = c0()
+    x, y, g1, g2, w = cat.arrays()
+    u0 = fp.estimate_4pcf_multipoles(x, y, g1, g2, w, edges, nmax)
+    um = fp.estimate_4pcf_multipoles(x, -y, g1, -g2, w, edges, nmax)
+    ur = fp.estimate_4pcf_multipoles(-y, x, -g1, -g2, w, edges, nmax)
+    assert np.all(rel_per_mu(um, np.conj(u0)) < 1e-12)
+    assert np.all(rel_per_mu(ur, u0) < 1e-12)
+
+
+def test_nan_catalogue_rejected(fp):
+    cat, edges, nmax = c0()
+    x = cat.x.copy()
+    x[17] = np.nan
+    with pytest.raises(fp.Fpcf4Error) as ei:
+        fp.estimate_4pcf_multipoles(x, cat.y, cat.g1, cat.g2, cat.w, edges, nmax)
+    assert ei.value.status == -1
+
+
+def test_natural_components_match_oracle(fp):
+    u = c0_ref(True)
+    gam, nrm = fp.to_natural(u, 8)
+    rg, rn = oracle.natural_components(u, 8)
+    assert np.allclose(nrm, rn, rtol=1e-12, atol=1e-12 * np.abs(rn).max())
+    sel = np.abs(rn) > 1e-6 * np.abs(rn).max()
+    assert np.allclose(gam[:, sel], rg[:, sel], rtol=1e-10, atol=1e-12)
+
+
+@functools.lru_cache(None)
+def grf1m():
+    cat, edges, nmax, _ = synth.workload("grf-1m")
+    return cat, edges, nmax
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_grf1m_sampled_centres(fp, prec):
+    """Full-size 1e6-galaxy GRF catalogue, 12 bins, nmax 10: a seeded sample of
+    centres with every galaxy as neighbour."""
+    cat, edges, nmax = grf1m()
+    idx = np.random.default_rng(11).choice(cat.n, 12, replace=False)
+    counts, _, _ = fp.debug_multipoles(*cat.arrays(), edges, nmax, precision=prec, centers=idx)
+    assert np.array_equal(counts, oracle.bin_counts(cat.x, cat.y, edges, idx))
+    got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision=prec, centers=idx)
+    ref = oracle.upsilon(*cat.arrays(), edges, nmax, centers=idx)
+    err = rel_per_mu(got, ref)
+    print(prec, err)
+    assert np.all(err < TOL[prec]), err
