@@ -127,22 +127,79 @@ template <typename T> __device__ __forceinline__ T rsq(T v);
 template <> __device__ __forceinline__ float rsq<float>(float v) { return __frsqrt_rn(v); }
 template <> __device__ __forceinline__ double rsq<double>(double v) { return rsqrt(v); }
 
-// Sum unit 64*M + lane over all 64 lanes (transposing butterfly).
+// Cross-lane primitives of the transposing butterfly.  swap32/swap16
+// exchange halves between two registers (v_permlane32_swap /
+// v_permlane16_swap): afterwards r0 + r1 holds, in lanes 0-31 (rows 0, 2),
+// the pair sums of the first register and in lanes 32-63 (rows 1, 3) those
+// of the second.  dpp(v, ctrl) reads the partner lane given by a DPP pattern
+// (row mirror, half-row mirror, quad permutations).
+__device__ __forceinline__ float swap_add32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap_add16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double swap_add32(double a, double b) {
+  const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0])) +
+         __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ __forceinline__ double swap_add16(double a, double b) {
+  const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0])) +
+         __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+constexpr int DPP_ROW_MIRROR = 0x140;       // lane i <- 15 - i within 16
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;  // lane i <- 7 - i within 8
+constexpr int DPP_QUAD_XOR2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int DPP_QUAD_XOR1 = 0xB1;         // quad_perm [1,0,3,2]
+
+// One level of the butterfly for partner patterns that swap the lane bit
+// `bit`: lanes with the bit clear keep the lower half of the live values.
+template <typename T, int D, int CTRL>
+__device__ __forceinline__ void level_dpp(T* v, unsigned lane, unsigned bit) {
+  const bool up = (lane & bit) != 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const T lo = v[k] + dpp<CTRL>(v[k]);
+    const T hi = v[k + D] + dpp<CTRL>(v[k + D]);
+    v[k] = up ? hi : lo;
+  }
+}
+
+// Sum unit 64*M + lane over all 64 lanes (transposing butterfly): each level
+// pairs lanes that hold the same live units and halves that set, so lane l
+// ends with the complete sum of unit 64*M + l.
 template <typename T, int NU, int M>
 __device__ __forceinline__ T butterfly_block(const T* acc, unsigned lane) {
   T v[64];
 #pragma unroll
   for (int k = 0; k < 64; ++k) v[k] = (64 * M + k < NU) ? acc[64 * M + k] : T(0);
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const bool hi = (lane & d) != 0;
+  for (int k = 0; k < 32; ++k) v[k] = swap_add32(v[k], v[k + 32]);   // lane bit 5
 #pragma unroll
-    for (int k = 0; k < d; ++k) {
-      const T send = hi ? v[k] : v[k + d];
-      const T keep = hi ? v[k + d] : v[k];
-      v[k] = keep + __shfl_xor(send, d, 64);
-    }
-  }
+  for (int k = 0; k < 16; ++k) v[k] = swap_add16(v[k], v[k + 16]);   // lane bit 4
+  level_dpp<T, 8, DPP_ROW_MIRROR>(v, lane, 8);
+  level_dpp<T, 4, DPP_ROW_HALF_MIRROR>(v, lane, 4);
+  level_dpp<T, 2, DPP_QUAD_XOR2>(v, lane, 2);
+  level_dpp<T, 1, DPP_QUAD_XOR1>(v, lane, 1);
   return v[0];
 }
 

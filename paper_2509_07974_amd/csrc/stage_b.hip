@@ -6,10 +6,8 @@
 //   P13[b][b2][n2]  nb*nb*nn   : sum_i x c13(i,b; n2) B(i,b2; n2)
 //   P23[b1][b][s]   nb*nb*ns   : sum_i x A(i,b1; s) c23(i,b; s), s = n2+n3
 //   P3[b]           nb         : sum_i x t(i,b)
-// One workgroup of up to 8 waves per (mu, kind, order, bin group); each wave
-// owns one equal-bin value b and all nb values of the other bin; lanes run over
-// the tile's centres (records are centre-contiguous, so loads coalesce) and
-// the 64 partial sums are combined at the end.
+// Records are centre-contiguous, so a chunk of centres of one bin row is a
+// coalesced load.
 #include "factors.hpp"
 #include "fpcf4_internal.hpp"
 
@@ -52,8 +50,17 @@ __device__ __forceinline__ cplx fac_val(const Rec<T>& R, const Layout& L, const 
   return f.conj ? cconj(v) : v;
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int CKC = 32;   // centres per LDS chunk
+
+// Each (mu, kind, order) is a small GEMM over the tile's centres,
+//   P[b_eq, b'] = sum_c E[c, b_eq] F[c, b'],  E = x (Table 1 block), F = other factor,
+// done on v_mfma_f64_16x16x4_f64 with the complex product split into real
+// rows [[E_r, -E_i], [E_i, E_r]] and columns [F_r; F_i].  The triple term
+// (kind 3) is the same GEMM with F = 1 in column 0.  The four waves take
+// alternate K-steps of each LDS-staged chunk and are summed at the end.
 template <typename T>
-__global__ __launch_bounds__(512) void corr_kernel(CorrArgs a) {
+__global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   const int nb = a.nb, n = a.nmax, nn = 2 * n + 1, ns = 4 * n + 1;
   const Layout L = make_layout(n);
   const int per_mu = 2 * nn + ns + 1;
@@ -64,8 +71,7 @@ __global__ __launch_bounds__(512) void corr_kernel(CorrArgs a) {
   else if ((r -= nn) < nn) { kind = 1; ord = r - n; }
   else if ((r -= nn) < ns) { kind = 2; ord = r - 2 * n; }
   else { kind = 3; }
-  const int lane = threadIdx.x & 63, beq = 8 * blockIdx.y + (threadIdx.x >> 6);   // wave -> equal bin
-  if (beq >= nb || (kind == 3 && beq > 0)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const MuFactors F = mu_factors(mu);
   const MuCorr C = mu_corr(mu);
   const Rec<T> R{reinterpret_cast<const T*>(a.rec), nb, a.ldc};
@@ -81,61 +87,106 @@ __global__ __launch_bounds__(512) void corr_kernel(CorrArgs a) {
   const int ce_fam = ce.fam;
   const int t_entry = L.offS + C.t;
   const int xkind = F.x;
+  const int ncent = a.ncent;
 
-  cplx acc[16];
-#pragma unroll
-  for (int b = 0; b < 16; ++b) acc[b] = {0.0, 0.0};
+  __shared__ cplx Es[2][16][CKC + 1];
+  __shared__ cplx Fs[2][16][CKC + 1];
+  __shared__ d4 red[4][2][64];
 
-  for (int c = lane; c < a.ncent; c += 64) {
-    cplx x;
-    if (xkind == X_W) x = {(double)xw[c], 0.0};
-    else {
-      x = {(double)xg[2 * c], (double)xg[2 * c + 1]};
-      if (xkind == X_GC) x.i = -x.i;
-    }
-    if (kind == 3) {
+  cplx pe[2], pf[2], px[2];
+  auto issue = [&](int c0) {
 #pragma unroll
-      for (int b = 0; b < 16; ++b) {
-        if (b < nb) {
-          const cplx v = cmul(x, R.at(t_entry, b, c));
-          acc[b].r += v.r;
-          acc[b].i += v.i;
-        }
-      }
-    } else {
-      const cplx e0 = cmul(x, corr_fam(R, L, ce_fam, ke, beq, c));
-#pragma unroll
-      for (int b = 0; b < 16; ++b) {
-        if (b < nb) {
-          cplx f = R.at(e_fo, b, c);
-          if (fo_conj) f.i = -f.i;
-          const cplx v = cmul(e0, f);
-          acc[b].r += v.r;
-          acc[b].i += v.i;
+    for (int h = 0; h < 2; ++h) {
+      const int slot = tid + 256 * h;
+      const int b = slot / CKC, c = c0 + slot % CKC;
+      pe[h] = pf[h] = px[h] = {0.0, 0.0};
+      if (b < nb && c < ncent) {
+        if (xkind == X_W) px[h] = {(double)xw[c], 0.0};
+        else px[h] = {(double)xg[2 * c], (double)xg[2 * c + 1]};
+        if (kind == 3) {
+          pe[h] = R.at(t_entry, b, c);
+          pf[h] = {b == 0 ? 1.0 : 0.0, 0.0};
+        } else {
+          pe[h] = corr_fam(R, L, ce_fam, ke, b, c);
+          pf[h] = R.at(e_fo, b, c);
         }
       }
     }
+  };
+  auto commit = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int slot = tid + 256 * h;
+      const int b = slot / CKC, cc = slot % CKC;
+      if (b < nb) {
+        cplx x = px[h];
+        if (xkind == X_GC) x.i = -x.i;
+        cplx f = pf[h];
+        if (kind != 3 && fo_conj) f.i = -f.i;
+        Es[buf][b][cc] = cmul(x, pe[h]);
+        Fs[buf][b][cc] = f;
+      }
+    }
+  };
+
+  // A rows (part, b_eq) of this lane in the two row tiles; B column b'
+  int rb[2], rp[2];
+  bool rok[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int row = 16 * m + (lane & 15);
+    rok[m] = row < 2 * nb;
+    rp[m] = rok[m] ? row / nb : 0;
+    rb[m] = rok[m] ? row % nb : 0;
   }
-  // combine the 64 lane partial sums
+  const int col = lane & 15;
+  const bool cok = col < nb;
+  const int kq = lane >> 4;   // K index within the 4-wide step: centre kq/2, part kq%2
+  d4 acc[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
+
+  const int nchunks = (ncent + CKC - 1) / CKC;
+  issue(0);
+  commit(0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nchunks;
+    if (more) issue((ch + 1) * CKC);
 #pragma unroll
-  for (int b = 0; b < 16; ++b)
+    for (int q = 0; q < CKC / 8; ++q) {         // this wave's K-steps: wv, wv+4, ...
+      const int ks = wv + 4 * q;
+      const int cc = 2 * ks + (kq >> 1), pk = kq & 1;
+      const cplx fv = Fs[buf][cok ? col : 0][cc];
+      const double bv = cok ? (pk ? fv.i : fv.r) : 0.0;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-      acc[b].r += __shfl_xor(acc[b].r, d, 64);
-      acc[b].i += __shfl_xor(acc[b].i, d, 64);
+      for (int m = 0; m < 2; ++m) {
+        const cplx ev = Es[buf][rb[m]][cc];
+        const double av = rok[m] ? (rp[m] ? (pk ? ev.r : ev.i) : (pk ? -ev.i : ev.r)) : 0.0;
+        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[m], 0, 0, 0);
+      }
     }
-  if (lane != 0) return;
+    if (more) commit(buf ^ 1);
+    __syncthreads();
+  }
+  red[wv][0][lane] = acc[0];
+  red[wv][1][lane] = acc[1];
+  __syncthreads();
+  if (wv != 0) return;
   double* out = a.corr + 2 * (int64_t)mu * corr_mu_elems(nb, n);
 #pragma unroll
-  for (int b = 0; b < 16; ++b) {
-    if (b < nb) {
+  for (int m = 0; m < 2; ++m) {
+    const d4 v = red[0][m][lane] + red[1][m][lane] + red[2][m][lane] + red[3][m][lane];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 16 * m + 4 * e + (lane >> 4);   // f64 D layout
+      if (row >= 2 * nb || !cok || (kind == 3 && col != 0)) continue;
+      const int part = row / nb, beq = row % nb, bo = col;
       int64_t o;
-      if (kind == 0) o = ((int64_t)beq * nb + b) * nn + (ord + n);
-      else if (kind == 1) o = (int64_t)nb * nb * nn + ((int64_t)beq * nb + b) * nn + (ord + n);
-      else if (kind == 2) o = 2LL * nb * nb * nn + ((int64_t)b * nb + beq) * ns + (ord + 2 * n);
-      else o = 2LL * nb * nb * nn + (int64_t)nb * nb * ns + b;
-      out[2 * o] += acc[b].r;
-      out[2 * o + 1] += acc[b].i;
+      if (kind == 0) o = ((int64_t)beq * nb + bo) * nn + (ord + n);
+      else if (kind == 1) o = (int64_t)nb * nb * nn + ((int64_t)beq * nb + bo) * nn + (ord + n);
+      else if (kind == 2) o = 2LL * nb * nb * nn + ((int64_t)bo * nb + beq) * ns + (ord + 2 * n);
+      else o = 2LL * nb * nb * nn + (int64_t)nb * nb * ns + beq;
+      out[2 * o + part] += v[e];
     }
   }
 }
@@ -145,8 +196,7 @@ hipError_t launch_corrections(const CorrArgs& a, hipStream_t s) {
   if (a.ncent <= 0) return hipSuccess;
   const int nn = 2 * a.nmax + 1, ns = 4 * a.nmax + 1;
   const int blocks = 9 * (2 * nn + ns + 1);
-  const int waves = a.nb < 8 ? a.nb : 8;
-  hipLaunchKernelGGL(corr_kernel<T>, dim3(blocks, (a.nb + 7) / 8), dim3(64 * waves), 0, s, a);
+  hipLaunchKernelGGL(corr_kernel<T>, dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 template hipError_t launch_corrections<double>(const CorrArgs&, hipStream_t);

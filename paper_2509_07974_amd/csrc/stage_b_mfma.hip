@@ -106,15 +106,21 @@ struct Half8<FPCF4_MIXED_BF16> {
   typedef bh8 type;
 };
 
+typedef __fp16 h2 __attribute__((ext_vector_type(2)));
+
 template <int PREC>
 __device__ __forceinline__ void split8v(const float (&v)[8], typename Half8<PREC>::type& hi,
                                         typename Half8<PREC>::type& lo) {
   if constexpr (PREC == FPCF4_MIXED_FP16) {
+    // hi = v rounded toward zero to fp16 (two per instruction); lo = fp16(v - hi)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const _Float16 h = (_Float16)v[q];
-      hi[q] = h;
-      lo[q] = (_Float16)(v[q] - (float)h);
+    for (int q = 0; q < 8; q += 2) {
+      const h2 hh = __builtin_amdgcn_cvt_pkrtz(v[q], v[q + 1]);
+      const h2 ll = __builtin_amdgcn_cvt_pkrtz(v[q] - (float)hh[0], v[q + 1] - (float)hh[1]);
+      hi[q] = (_Float16)hh[0];
+      hi[q + 1] = (_Float16)hh[1];
+      lo[q] = (_Float16)ll[0];
+      lo[q + 1] = (_Float16)ll[1];
     }
   } else {
 #pragma unroll
@@ -185,8 +191,9 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
   constexpr int famB = F0.B.fam == F_G ? 0 : 16;
   constexpr int famC = F0.C.fam == F_G ? 0 : 16;
 
-  __shared__ C2<float> Xs[2][16][KC];
-  __shared__ C2<float> Zs[2][16][KC];
+  // rows padded by one element: rows of different bins start in different LDS banks
+  __shared__ C2<float> Xs[2][16][KC + 1];
+  __shared__ C2<float> Zs[2][16][KC + 1];
   __shared__ H8 Ys[2][KS][MT][2][64];   // split Y operand in MFMA lane order
   __shared__ float sc_lds[3][16];       // scales of X (per b1), Y (b2), Z (b3)
 
@@ -210,6 +217,25 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
   const C2<float>* xg = reinterpret_cast<const C2<float>*>(a.xg);
   const float* xw = reinterpret_cast<const float*>(a.xw);
   Prefetch<float> pf;
+  // this thread's two Y slots (K-step, row tile, lane) and their row meaning
+  int y_ks[2], y_m[2], y_l[2], y_part[2], y_b2[2], y_row[2], y_cj[2];
+  bool y_ok[2], y_on[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int q = tid + 256 * h;
+    y_ks[h] = q / (MT * 64);
+    y_m[h] = (q / 64) % MT;
+    y_l[h] = q & 63;
+    y_on[h] = y_ks[h] < KS;
+    const int r = 16 * y_m[h] + (y_l[h] & 15);
+    y_ok[h] = y_on[h] && r < mrows;
+    const int rr = y_ok[h] ? r : 0;
+    const int mi = rr / (2 * nb);
+    y_part[h] = (rr % (2 * nb)) / nb;
+    y_b2[h] = rr % nb;
+    y_row[h] = (mi ? rowB1 : rowB0) * nb + y_b2[h];
+    y_cj[h] = mi ? F1.B.conj : F0.B.conj;
+  }
   auto issue = [&](int c0) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -227,18 +253,13 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int q = tid + 256 * h;             // (K-step, row tile, lane) slot of Y
-      const int ks = q / (MT * 64), m = (q / 64) % MT, l = q & 63;
-      const int r = 16 * m + (l & 15);
 #pragma unroll
       for (int u = 0; u < 4; ++u) pf.y[h][u] = {0.f, 0.f};
-      if (ks < KS && r < mrows) {
-        const int mi = r / (2 * nb), b2 = r % nb;
-        const int rowB = mi ? rowB1 : rowB0;
+      if (y_ok[h]) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int c = c0 + 16 * ks + 4 * (l >> 4) + u;
-          if (c < ncent) pf.y[h][u] = ldrec(rec, (int64_t)rowB * nb + b2, ldc, c);
+          const int c = c0 + 16 * y_ks[h] + 4 * (y_l[h] >> 4) + u;
+          if (c < ncent) pf.y[h][u] = ldrec(rec, (int64_t)y_row[h], ldc, c);
         }
       }
     }
@@ -260,19 +281,15 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int q = tid + 256 * h;
-      const int ks = q / (MT * 64), m = (q / 64) % MT, l = q & 63;
-      if (ks >= KS) continue;
-      const int r = 16 * m + (l & 15);
+      if (!y_on[h]) continue;
       float v[8];
-      if (r < mrows) {
-        const int mi = r / (2 * nb), part = (r % (2 * nb)) / nb, b2 = r % nb;
-        const int cjB = mi ? F1.B.conj : F0.B.conj;
-        const float sy = sc_lds[1][b2];
+      if (y_ok[h]) {
+        const int part = y_part[h];
+        const float sy = sc_lds[1][y_b2[h]];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           C2<float> y = pf.y[h][u];
-          if (cjB) y.i = -y.i;
+          if (y_cj[h]) y.i = -y.i;
           // row part 0 (real out): [ y_r, -y_i ];  part 1 (imag out): [ y_i, y_r ]
           v[2 * u] = (part ? y.i : y.r) * sy;
           v[2 * u + 1] = (part ? y.r : -y.i) * sy;
@@ -283,12 +300,13 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
       }
       H8 hi, lo;
       split8v<PREC>(v, hi, lo);
-      Ys[buf][ks][m][0][l] = hi;
-      Ys[buf][ks][m][1][l] = lo;
+      Ys[buf][y_ks[h]][y_m[h]][0][y_l[h]] = hi;
+      Ys[buf][y_ks[h]][y_m[h]][1][y_l[h]] = lo;
     }
   };
 
-  // per-lane column (b1, b3) of each of this wave's tiles
+  // per-lane column (b1, b3) of each of this wave's tiles; padding columns
+  // read the zero row nb of the X buffer (nb < 16 whenever nb^2 % 16 != 0)
   int b1c[NTW], b3c[NTW];
   bool colok[NTW], tok[NTW];
 #pragma unroll
@@ -297,8 +315,12 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
     const int j = 16 * T + (lane & 15);
     tok[t] = T < ntiles;
     colok[t] = tok[t] && (j < ncols);
-    b1c[t] = colok[t] ? j / nb : 0;
+    b1c[t] = colok[t] ? j / nb : (nb < 16 ? nb : 0);
     b3c[t] = colok[t] ? j % nb : 0;
+  }
+  for (int z = tid; z < 2 * 16 * (KC + 1); z += 256) {
+    const int bb = (z / (KC + 1)) % 16;
+    if (bb >= nb) Xs[z / (16 * (KC + 1))][bb][z % (KC + 1)] = {0.f, 0.f};
   }
 
   f4 acc[MT][NTW];
@@ -338,8 +360,8 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
         for (int u = 0; u < 4; ++u) {
           const C2<float> xv = Xs[buf][b1c[t]][cb + u];
           const C2<float> zv = Zs[buf][b3c[t]][cb + u];
-          v[2 * u] = colok[t] ? xv.r * zv.r - xv.i * zv.i : 0.f;
-          v[2 * u + 1] = colok[t] ? xv.r * zv.i + xv.i * zv.r : 0.f;
+          v[2 * u] = xv.r * zv.r - xv.i * zv.i;
+          v[2 * u + 1] = xv.r * zv.i + xv.i * zv.r;
         }
         H8 rh, rl;
         split8v<PREC>(v, rh, rl);
@@ -415,9 +437,9 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(BArgs a) {
   const int rowB0 = fac_entry_k(L, F0.B, F0.B.a * n2 + F0.B.c);
   const int rowB1 = fac_entry_k(L, F1.B, F1.B.a * n2 + F1.B.c);
 
-  __shared__ C2<double> Xs[2][16][KC];
-  __shared__ C2<double> Zs[2][16][KC];
-  __shared__ C2<double> Ys[2][GR.nmu][16][KC];   // [mu idx][b2][centre]
+  __shared__ C2<double> Xs[2][16][KC + 1];
+  __shared__ C2<double> Zs[2][16][KC + 1];
+  __shared__ C2<double> Ys[2][GR.nmu][16][KC + 1];   // [mu idx][b2][centre]
 
   const C2<double>* xg = reinterpret_cast<const C2<double>*>(a.xg);
   const double* xw = reinterpret_cast<const double*>(a.xw);
