@@ -16,7 +16,7 @@ hipError_t cells_bbox(const double*, const double*, const double*, const double*
 size_t cells_sort_temp_bytes(int64_t n);
 hipError_t cells_build(const double*, const double*, const double*, const double*, const double*,
                        int64_t, const Grid&, uint32_t*, uint32_t*, int32_t*, int32_t*, void*, size_t,
-                       double*, double*, double*, double*, double*, int32_t*, int32_t*, hipStream_t);
+                       void*, int, int32_t*, int32_t*, hipStream_t);
 hipError_t cells_centre_order(const uint32_t*, int64_t, const Grid&, uint32_t*, uint32_t*, int32_t*,
                               int32_t*, void*, size_t, hipStream_t);
 hipError_t cells_map_centres(const int64_t*, int64_t, const int32_t*, int32_t*, hipStream_t);
@@ -62,7 +62,7 @@ struct PlanInfo {
   int64_t ncell_cap = 0;
   size_t sort_tmp = 0;
   // persistent buffers
-  size_t o_x, o_y, o_fa, o_fb, o_fw, o_cells, o_centres, o_e2, o_edges, o_counters, o_bbox, o_bad,
+  size_t o_gal, o_cells, o_centres, o_e2, o_edges, o_counters, o_bbox, o_bad,
       o_pairs, o_part, o_ups, o_corr, o_xg, o_xw, o_counts, o_aos, o_region;
   size_t region = 0;           // records of one tile, or create-time temporaries
   // create-time temporaries inside the region
@@ -127,11 +127,7 @@ fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
 
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += up(bytes); return o; };
-  P.o_x = take(n * 8);
-  P.o_y = take(n * 8);
-  P.o_fa = take(n * 8);
-  P.o_fb = take(n * 8);
-  P.o_fw = take(n * 8);
+  P.o_gal = take(n * (P.precision == FPCF4_FP64 ? sizeof(Gal<double>) : sizeof(Gal<float>)));
   P.o_cells = take((P.ncell_cap + 1) * 4);
   P.o_centres = take((size_t)std::max<int64_t>(P.ncent, 1) * 4);
   P.o_e2 = take((P.nb + 1) * 8);
@@ -290,8 +286,8 @@ fpcf4_status request_init(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   int32_t* inv = reinterpret_cast<int32_t*>(reg + P.t_inv);
   void* sort_tmp = reg + P.t_sort;
   HIPCHK(cells_build(x, y, g1, g2, w, n, g, key_a, key_b, idx_a, idx_b, sort_tmp, P.sort_tmp,
-                     R->at<double>(P.o_x), R->at<double>(P.o_y), R->at<double>(P.o_fa),
-                     R->at<double>(P.o_fb), R->at<double>(P.o_fw), R->at<int32_t>(P.o_cells), inv, s));
+                     R->ws + P.o_gal, P.precision == FPCF4_FP64 ? 1 : 0, R->at<int32_t>(P.o_cells),
+                     inv, s));
   int32_t* centres = R->at<int32_t>(P.o_centres);
   if (opts->centers) {
     if (P.ncent > 0) {
@@ -331,11 +327,7 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
   HIPCHK(hipGetLastError());
   StageAArgs a{};
   a.cat.n = P.n;
-  a.cat.x = R->at<double>(P.o_x);
-  a.cat.y = R->at<double>(P.o_y);
-  a.cat.fa = R->at<double>(P.o_fa);
-  a.cat.fb = R->at<double>(P.o_fb);
-  a.cat.fw = R->at<double>(P.o_fw);
+  a.cat.gal = R->ws + P.o_gal;
   a.cat.cell_start = R->at<int32_t>(P.o_cells);
   a.cat.g = R->grid;
   a.centres = R->at<int32_t>(P.o_centres) + c0;
@@ -352,17 +344,14 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
   a.counts = R->want_counts ? R->at<int32_t>(P.o_counts) : nullptr;
   a.work_counter = counters;
   a.pairs = R->at<unsigned long long>(P.o_pairs);
-  int npass = 0;
-  if (P.precision == FPCF4_FP64) HIPCHK(launch_stage_a<double>(P.nmax, a, s, &npass));
-  else HIPCHK(launch_stage_a<float>(P.nmax, a, s, &npass));
+  int nlaunch = 0;
+  if (P.precision == FPCF4_FP64) HIPCHK(launch_stage_a<double>(P.nmax, a, s, &nlaunch));
+  else HIPCHK(launch_stage_a<float>(P.nmax, a, s, &nlaunch));
   if (prof) HIPCHK(hipEventRecord(evs[1], s));
   if (stage_b) {
     StageBArgs b{};
     b.rec = a.rec;
     b.centres = a.centres;
-    b.fa = a.cat.fa;
-    b.fb = a.cat.fb;
-    b.fw = a.cat.fw;
     b.ncent = ncent;
     b.nb = P.nb;
     b.nmax = P.nmax;
@@ -375,7 +364,7 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
     else HIPCHK(launch_corrections<float>(ca, s));
     if (prof) {
       HIPCHK(hipEventRecord(evs[3], s));
-      R->prof_a_launches += npass;
+      R->prof_a_launches += nlaunch;
       R->prof_b_launches += 7;
       R->prof_steps += 1;
       R->prof_centres += ncent;

@@ -5,7 +5,8 @@
 //  key_kernel     : cell key cy * ncx + cx of every galaxy
 //  (hipcub radix sort of (key, index) pairs: stable, deterministic)
 //  starts_kernel  : cell_start[c] = first sorted position of cell c
-//  gather_kernel  : sorted SoA x, y, w g1, w g2, w and the inverse permutation
+//  gather_kernel  : sorted galaxy records (x, y, w g1, w g2, w) and the
+//                   inverse permutation
 //  morton_kernel  : Morton key of each sorted galaxy's cell, so that the
 //                   centre list (sorted by it) visits space in compact blocks
 #include <hipcub/hipcub.hpp>
@@ -93,19 +94,21 @@ __global__ void starts_kernel(const uint32_t* skey, int64_t n, int64_t ncells, i
   }
 }
 
+template <typename T>
 __global__ void gather_kernel(const double* x, const double* y, const double* g1,
                               const double* g2, const double* w, const int32_t* perm,
-                              int64_t n, double* xs, double* ys, double* fa, double* fb,
-                              double* fw, int32_t* inv) {
+                              int64_t n, Gal<T>* gal, int32_t* inv) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t p = perm[i];
     const double wv = w[p];
-    xs[i] = x[p];
-    ys[i] = y[p];
-    fa[i] = wv * g1[p];
-    fb[i] = wv * g2[p];
-    fw[i] = wv;
+    Gal<T> r{};
+    r.x = x[p];
+    r.y = y[p];
+    r.a = (T)(wv * g1[p]);
+    r.b = (T)(wv * g2[p]);
+    r.w = (T)wv;
+    gal[i] = r;
     if (inv) inv[p] = (int32_t)i;
   }
 }
@@ -167,12 +170,13 @@ static int bits_for(uint64_t v) {
   return b;
 }
 
-// Builds the sorted SoA and cell starts.  All scratch arrays are caller-provided.
+// Builds the sorted galaxy records and cell starts.  All scratch arrays are
+// caller-provided; gal holds Gal<double> when fp64 != 0, else Gal<float>.
 hipError_t cells_build(const double* x, const double* y, const double* g1, const double* g2,
                        const double* w, int64_t n, const Grid& g, uint32_t* key_a,
                        uint32_t* key_b, int32_t* idx_a, int32_t* idx_b, void* sort_tmp,
-                       size_t sort_tmp_bytes, double* xs, double* ys, double* fa, double* fb,
-                       double* fw, int32_t* cell_start, int32_t* inv, hipStream_t s) {
+                       size_t sort_tmp_bytes, void* gal, int fp64, int32_t* cell_start,
+                       int32_t* inv, hipStream_t s) {
   const int64_t ncells = (int64_t)g.ncx * g.ncy;
   hipLaunchKernelGGL(key_kernel, dim3(grid1d(n)), dim3(256), 0, s, x, y, n, g, key_a, idx_a);
   size_t tb = sort_tmp_bytes;
@@ -180,8 +184,12 @@ hipError_t cells_build(const double* x, const double* y, const double* g1, const
                                                     0, bits_for((uint64_t)ncells), s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(starts_kernel, dim3(grid1d(n + 1)), dim3(256), 0, s, key_b, n, ncells, cell_start);
-  hipLaunchKernelGGL(gather_kernel, dim3(grid1d(n)), dim3(256), 0, s, x, y, g1, g2, w, idx_b, n,
-                     xs, ys, fa, fb, fw, inv);
+  if (fp64)
+    hipLaunchKernelGGL(gather_kernel<double>, dim3(grid1d(n)), dim3(256), 0, s, x, y, g1, g2, w, idx_b,
+                       n, reinterpret_cast<Gal<double>*>(gal), inv);
+  else
+    hipLaunchKernelGGL(gather_kernel<float>, dim3(grid1d(n)), dim3(256), 0, s, x, y, g1, g2, w, idx_b,
+                       n, reinterpret_cast<Gal<float>*>(gal), inv);
   return hipGetLastError();
 }
 

@@ -72,14 +72,21 @@ struct Grid {
   int ncx, ncy;
 };
 
-// Sorted structure-of-arrays catalogue on the device.
+// One galaxy of the spatially sorted catalogue (array of structures, one
+// 16-byte aligned record per galaxy so a neighbour costs two or three vector
+// loads).  The weights are pre-multiplied: a = w g1, b = w g2, and they are
+// held in the accumulation type of stage (a) (binary32 in the mixed paths,
+// rounded once from the binary64 products).  Positions stay binary64: the
+// bin decision is taken on binary64 separations.
+template <typename T> struct alignas(16) Gal;
+template <> struct alignas(16) Gal<float> { double x, y; float a, b, w, pad; };
+template <> struct alignas(16) Gal<double> { double x, y, a, b, w, pad; };
+static_assert(sizeof(Gal<float>) == 32 && sizeof(Gal<double>) == 48, "galaxy record size");
+
+// Sorted catalogue on the device.
 struct SortedCat {
   int64_t n;
-  const double* x;
-  const double* y;
-  const double* fa;   // w g1
-  const double* fb;   // w g2
-  const double* fw;   // w
+  const void* gal;            // Gal<T>[n], T = accumulation type of stage (a)
   const int32_t* cell_start;  // [ncx*ncy + 1]
   Grid g;
 };
@@ -98,20 +105,17 @@ struct StageAArgs {
   void* xw;                 // [ldc] (T): w of each tile centre
   unsigned* maxima;         // fp16 scaling maxima (float bits) or null
   int32_t* counts;          // [ncent][nb] or null
-  int32_t* work_counter;    // dynamic centre scheduling counters [8 per pass]
+  int32_t* work_counter;    // dynamic centre scheduling counters, one per XCD
   unsigned long long* pairs;  // in-bin pair counter (may be null)
 };
 
 // stage (a) launcher, T = double or float; returns the number of kernel
-// launches (passes) in *npass
-template <typename T> hipError_t launch_stage_a(int nmax, const StageAArgs& a, hipStream_t s, int* npass);
+// launches in *nlaunch
+template <typename T> hipError_t launch_stage_a(int nmax, const StageAArgs& a, hipStream_t s, int* nlaunch);
 
 struct StageBArgs {
   const void* rec;          // records of the tile
   const int32_t* centres;   // sorted positions of the tile's centres
-  const double* fa;
-  const double* fb;
-  const double* fw;
   int32_t ncent;
   int32_t nb;
   int32_t nmax;

@@ -15,19 +15,21 @@
 // so accumulating only k >= 0 halves the complex multiply-adds.
 //
 // Mapping on CDNA4 (wave64):
-//  * one wavefront owns one centre at a time (dynamic per-XCD queues, with
-//    stealing, over a Morton-ordered centre list);
-//  * for each bin the wave walks the rows of the cell grid that intersect
-//    the annulus (row bounds computed lane-parallel, one row per lane); the
-//    64 lanes load 64 consecutive neighbours (coalesced SoA), form r^2 in
-//    binary64 without contraction and test the bin against the squared
-//    edges -- the same arithmetic as the oracle, so binning is bit-exact;
-//  * in-bin neighbours are compacted with a ballot into a wave-private LDS
-//    ring; every full batch of 64 is consumed with all lanes busy: each
-//    lane computes z, its power chain z^k and accumulates its own partial
-//    sums in registers;
-//  * the accumulators of a pass cover an order range [K0, K1] sized to the
-//    register file; several passes cover all orders;
+//  * one workgroup owns one centre at a time (dynamic per-XCD queues, with
+//    stealing, over a Morton-ordered centre list); its W waves each own one
+//    pass, i.e. one range of orders k whose accumulators fit the register
+//    file (the units of all passes together cover every order once);
+//  * for each bin the annulus is a list of row segments of the cell grid
+//    (row bounds computed lane-parallel, one row per lane); the workgroup
+//    walks its flat candidate list in rounds of W chunks of 64: wave w loads
+//    chunk W r + w (one 32- or 48-byte galaxy record per lane), forms r^2 in
+//    binary64 without contraction and tests the bin against the squared
+//    edges -- the same arithmetic as the oracle, so binning is bit-exact --
+//    and compacts its in-bin neighbours with a ballot into LDS;
+//  * after one barrier per round every wave consumes all compacted
+//    neighbours of the round in full batches of 64 (each lane forms z, its
+//    power chain z^k and adds to its own partial sums), so the binning is
+//    done once and shared by every pass;
 //  * partial sums are combined across lanes by a transposing butterfly
 //    (log2 64 levels, halving the live values per level), so each lane ends
 //    with complete sums of its own units; the binary32 variant folds into
@@ -58,35 +60,38 @@ __host__ __device__ constexpr int total_units(int n) {
   for (int k = 0; k <= ktop(n); ++k) u += units_at(n, k);
   return u;
 }
-// Greedy split of the orders 0..ktop into passes of at most `cap` units;
-// pass 0 also holds the 15 special units (orders 0, 4, 8 of the triple
-// blocks, accumulated from z^4 and z^8 formed by squaring).  which: 0 = first
-// order of pass p, 1 = last order of pass p, 2 = number of passes.
-__host__ __device__ constexpr int greedy(int n, int cap, int p, int which) {
-  int np = 0, k = 0;
-  while (k <= ktop(n)) {
-    int used = (np == 0) ? NSPECIAL : 0;
+// Split of the orders 0..ktop into passes of at most `cap` accumulator
+// units each (greedy, in order); pass 0 also holds the 15 special units
+// (orders 0, 4, 8 of the triple blocks, accumulated from z^4 and z^8 formed
+// by squaring).
+struct PassPlan {
+  int np;
+  int k0[32], k1[32], units[32];
+};
+__host__ __device__ constexpr PassPlan greedy(int n, int cap) {
+  PassPlan P{};
+  int k = 0;
+  while (k <= ktop(n) && P.np < 32) {
+    int used = (P.np == 0) ? NSPECIAL : 0;
     const int start = k;
     while (k <= ktop(n) && (k == start || used + units_at(n, k) <= cap)) {
       used += units_at(n, k);
       ++k;
     }
-    if (np == p && which < 2) return which == 0 ? start : k - 1;
-    ++np;
+    P.k0[P.np] = start;
+    P.k1[P.np] = k - 1;
+    P.units[P.np] = used;
+    ++P.np;
   }
-  return which == 2 ? np : -1;
+  return P;
 }
 // Fewest passes within the register budget, then the smallest cap that
 // still needs no more passes (balanced passes).
-__host__ __device__ constexpr int plan_cap(int n, int budget) {
-  const int np = greedy(n, budget, 0, 2);
+__host__ __device__ constexpr PassPlan pass_plan(int n, int budget) {
+  const int np = greedy(n, budget).np;
   int cap = (total_units(n) + np - 1) / np;
-  while (greedy(n, cap, 0, 2) > np) ++cap;
-  return cap;
-}
-__host__ __device__ constexpr int plan_np(int n, int budget) { return greedy(n, plan_cap(n, budget), 0, 2); }
-__host__ __device__ constexpr int plan_k(int n, int budget, int p, int which) {
-  return greedy(n, plan_cap(n, budget), p, which);
+  while (greedy(n, cap).np > np) ++cap;
+  return greedy(n, cap);
 }
 __host__ __device__ constexpr int ubase(int n, int k0, int k) {
   int b = 0;
@@ -101,8 +106,8 @@ __host__ __device__ constexpr int uidx(int n, int k0, int f, int k) {
 }
 
 template <typename T> struct Budget;
-template <> struct Budget<float> { static constexpr int units = 150; static constexpr int fold = 32; };
-template <> struct Budget<double> { static constexpr int units = 84; static constexpr int fold = 1 << 30; };
+template <> struct Budget<float> { static constexpr int units = 96; static constexpr int fold = 32; };
+template <> struct Budget<double> { static constexpr int units = 48; static constexpr int fold = 1 << 30; };
 
 __device__ __forceinline__ double r2_exact(double dx, double dy) {
 #pragma clang fp contract(off)
@@ -211,8 +216,6 @@ __device__ __forceinline__ void fold_all(T* acc, double* mst, unsigned lane) {
   }
 }
 
-constexpr int QCAP = 128;
-
 // Accumulate one neighbour (weights val[], power chain p = z^K starting at
 // K = K0) into the order units of the pass; all unit indices are
 // compile-time constants, so the accumulators stay in registers.
@@ -264,339 +267,429 @@ __device__ __forceinline__ void cpow(T zr, T zi, T& pr, T& pi) {
   }
 }
 
+// Add one in-bin neighbour (separation dx, dy; weights a = w g1, b = w g2,
+// w) to the units of one pass.  Lanes with valid == false add nothing.
+template <typename T, int N, int K0, int K1, bool P0, int NUO>
+__device__ __forceinline__ void add_pair(T* acc, bool valid, T dx, T dy, T va, T vb, T vw) {
+  if (!valid) {
+    dx = T(0); dy = T(0); va = T(0); vb = T(0); vw = T(0);
+  }
+  T val[NF];
+  val[FA] = va;
+  val[FB] = vb;
+  val[FC] = va * va - vb * vb;
+  val[FD] = T(2) * va * vb;
+  val[FW] = vw;
+  val[FE] = va * va + vb * vb;
+  val[FV] = vw * vw;
+  const T inv = valid ? rsq<T>(dx * dx + dy * dy) : T(0);
+  const T zr = dx * inv, zi = dy * inv;
+  T pr, pi;
+  cpow<T, K0>(zr, zi, pr, pi);
+  acc_orders<T, N, K0, K1, K0>(acc, val, pr, pi, zr, zi);
+  if constexpr (P0) {
+    // triple-counting blocks: T_-8, T_-4 (weight (w g)^3), M_-4, M_0
+    // (weight |w g|^2 w g) and U (weight w^3)
+    const T z2r = zr * zr - zi * zi, z2i = T(2) * zr * zi;
+    const T z4r = z2r * z2r - z2i * z2i, z4i = T(2) * z2r * z2i;
+    const T z8r = z4r * z4r - z4i * z4i, z8i = T(2) * z4r * z4i;
+    const T p3 = val[FC] * va - val[FD] * vb;   // Re (w g)^3
+    const T q3 = val[FC] * vb + val[FD] * va;   // Im (w g)^3
+    const T ea = val[FE] * va, eb = val[FE] * vb;
+    acc[NUO + 0] += p3 * z8r;
+    acc[NUO + 1] += p3 * z8i;
+    acc[NUO + 2] += q3 * z8r;
+    acc[NUO + 3] += q3 * z8i;
+    acc[NUO + 4] += p3 * z4r;
+    acc[NUO + 5] += p3 * z4i;
+    acc[NUO + 6] += q3 * z4r;
+    acc[NUO + 7] += q3 * z4i;
+    acc[NUO + 8] += ea * z4r;
+    acc[NUO + 9] += ea * z4i;
+    acc[NUO + 10] += eb * z4r;
+    acc[NUO + 11] += eb * z4i;
+    acc[NUO + 12] += ea;
+    acc[NUO + 13] += eb;
+    acc[NUO + 14] += vw * val[FV];
+  }
+}
+
+__host__ __device__ constexpr int max_blocks64(const PassPlan& P) {
+  int m = 1;
+  for (int p = 0; p < P.np; ++p) m = imax(m, (P.units[p] + 63) / 64);
+  return m;
+}
+
+template <typename T, int N> struct Conf {
+  static constexpr PassPlan PP = pass_plan(N, Budget<T>::units);
+  static constexpr int W = PP.np;        // waves per workgroup = passes
+  static constexpr int NMX = max_blocks64(PP);
+  static_assert(W >= 1 && W <= 16, "passes must fit one workgroup");
+};
+
+// In-bin neighbour handed from the binning lanes to every pass.
+template <typename T> struct alignas(16) QE { T dx, dy, a, b; };
+
+template <typename T, int W, int NMX> struct Shared {
+  QE<T> q[2][W][64];        // round buffers: wave w's compacted in-bin neighbours
+  T qw[2][W][64];
+  double stage[W][NMX * 64];  // per-wave epilogue staging of the binary64 sums
+  int rows[2][5][64];       // row table: s1, l1, s2, row length, inclusive prefix
+  int cnt[2][W];            // in-bin count of each wave's chunk
+  int cent[2];              // centre broadcast
+};
+
+// One wave = one pass (an order range of the accumulators).  The waves of a
+// workgroup share the walk: in every round wave w bins chunk (W r + w) of the
+// annulus' flat candidate list, compacts its in-bin neighbours into its slot
+// of the round buffer, and after one workgroup barrier every wave adds the
+// round's neighbours, in the fixed order (carry, wave 0, ..., wave W-1), to
+// its own units in full batches of 64; a remainder below 64 is carried in
+// registers into the next round.  The order is the same in every wave and
+// every run (no atomics), so results are reproducible bit for bit.
 template <typename T, int N, int PASS>
-__global__ __launch_bounds__(256) void stage_a_kernel(StageAArgs a) {
-  constexpr int BU = Budget<T>::units;
-  constexpr int K0 = plan_k(N, BU, PASS, 0);
-  constexpr int K1 = plan_k(N, BU, PASS, 1);
+__device__ __forceinline__ void pass_body(const StageAArgs& a,
+                                          Shared<T, Conf<T, N>::W, Conf<T, N>::NMX>& sh,
+                                          unsigned lane) {
+  constexpr int W = Conf<T, N>::W;
+  constexpr int K0 = Conf<T, N>::PP.k0[PASS];
+  constexpr int K1 = Conf<T, N>::PP.k1[PASS];
   constexpr bool P0 = (PASS == 0);
   constexpr int NUO = ubase(N, K0, K1 + 1);          // order units
   constexpr int NU = NUO + (P0 ? NSPECIAL : 0);
   constexpr int NM = (NU + 63) / 64;
   constexpr int FOLD = Budget<T>::fold;
+  static_assert(NM <= Conf<T, N>::NMX, "staging block");
 
-  // queue of in-bin neighbours: separation and weights (w g1, w g2, w)
-  __shared__ T q_dx[4][QCAP];
-  __shared__ T q_dy[4][QCAP];
-  __shared__ T q_va[4][QCAP];
-  __shared__ T q_vb[4][QCAP];
-  __shared__ T q_vw[4][QCAP];
-  __shared__ double stage[4][NM * 64];
-
-  const unsigned lane = lane_id();
-  const int wv = threadIdx.x >> 6;
-  const SortedCat& cat = a.cat;
-  const Grid g = cat.g;
+  const Gal<T>* __restrict__ gal = reinterpret_cast<const Gal<T>*>(a.cat.gal);
+  const Grid g = a.cat.g;
   const Layout L = make_layout(N);
   const int nb = a.nb;
 
   const int xcd0 = blockIdx.x & 7;
-  int32_t* counters = a.work_counter + 8 * PASS;
-  // per-wave running totals, flushed with one atomic each when the wave ends
+  int xs = 0;          // pass 0: XCD cursor of the centre grab
+  unsigned rc = 0;     // rounds so far (round-buffer parity)
+  unsigned tc = 0;     // centres so far (broadcast-slot parity)
+  unsigned tt = 0;     // row tables so far (table parity)
   unsigned long long wave_pairs = 0;
   float lane_gmax = 0.f, lane_wmax = 0.f;   // lane b: maxima of bin b
   float lane_xmax = 0.f, lane_wxmax = 0.f;  // lane 0: |w g| and |w| maxima
 
-  for (int xs = 0; xs < 8; ++xs) {
-    const int xcd = (xcd0 + xs) & 7;
-    const int lo = (int)(((int64_t)a.ncent * xcd) >> 3);
-    const int hi = (int)(((int64_t)a.ncent * (xcd + 1)) >> 3);
-    for (;;) {
-      int c = 0;
-      if (lane == 0) c = atomicAdd(counters + xcd, 1);
-      c = __shfl(c, 0, 64);
-      const int idx = lo + c;
-      if (idx >= hi) break;
-      const int i = a.centres[idx];
-      const double xi = cat.x[i];
-      const double yi = cat.y[i];
-
-      for (int b = 0; b < nb; ++b) {
-        const double e2lo = a.e2[b], e2hi = a.e2[b + 1];
-        // conservative culling radii and cell margin (binning itself is exact)
-        const double rin = a.edges[b] * (1.0 - 1e-9);
-        const double rout = a.edges[b + 1] * (1.0 + 1e-9);
-        const double dlt = 1e-9 * g.h;
-        int cy0 = (int)floor((yi - rout - g.y0) * g.inv_h) - 1;
-        int cy1 = (int)floor((yi + rout - g.y0) * g.inv_h) + 1;
-        cy0 = imax(cy0, 0);
-        cy1 = imin(cy1, g.ncy - 1);
-        const int nrows = cy1 - cy0 + 1;
-
-        T acc[NU];
-#pragma unroll
-        for (int u = 0; u < NU; ++u) acc[u] = T(0);
-        double mst[NM];
-#pragma unroll
-        for (int m = 0; m < NM; ++m) mst[m] = 0.0;
-        unsigned head = 0, tail = 0;
-        int nblk = 0;
-        int cnt = 0;
-
-        auto consume = [&](unsigned m) {
-          const bool valid = lane < m;
-          const unsigned e = (head + lane) & (QCAP - 1);
-          T dx = T(0), dy = T(0), va = T(0), vb = T(0), vw = T(0);
-          if (valid) {
-            dx = q_dx[wv][e];
-            dy = q_dy[wv][e];
-            va = q_va[wv][e];
-            vb = q_vb[wv][e];
-            vw = q_vw[wv][e];
+  for (;;) {
+    if constexpr (P0) {
+      // dynamic centre scheduling: the XCD's own range of the centre list
+      // first, then the other XCDs' ranges
+      if (lane == 0) {
+        int idx = -1;
+        while (xs < 8) {
+          const int xcd = (xcd0 + xs) & 7;
+          const int lo = (int)(((int64_t)a.ncent * xcd) >> 3);
+          const int hi = (int)(((int64_t)a.ncent * (xcd + 1)) >> 3);
+          const int c = atomicAdd(a.work_counter + xcd, 1);
+          if (lo + c < hi) {
+            idx = lo + c;
+            break;
           }
-          T val[NF];
-          val[FA] = va;
-          val[FB] = vb;
-          val[FC] = va * va - vb * vb;
-          val[FD] = T(2) * va * vb;
-          val[FW] = vw;
-          val[FE] = va * va + vb * vb;
-          val[FV] = vw * vw;
-          const T inv = valid ? rsq<T>(dx * dx + dy * dy) : T(0);
-          const T zr = dx * inv, zi = dy * inv;
-          T pr, pi;
-          cpow<T, K0>(zr, zi, pr, pi);
-          acc_orders<T, N, K0, K1, K0>(acc, val, pr, pi, zr, zi);
-          if constexpr (P0) {
-            // triple-counting blocks: T_-8, T_-4 (weight (w g)^3), M_-4, M_0
-            // (weight |w g|^2 w g) and U (weight w^3)
-            const T z2r = zr * zr - zi * zi, z2i = T(2) * zr * zi;
-            const T z4r = z2r * z2r - z2i * z2i, z4i = T(2) * z2r * z2i;
-            const T z8r = z4r * z4r - z4i * z4i, z8i = T(2) * z4r * z4i;
-            const T p3 = val[FC] * va - val[FD] * vb;   // Re (w g)^3
-            const T q3 = val[FC] * vb + val[FD] * va;   // Im (w g)^3
-            const T ea = val[FE] * va, eb = val[FE] * vb;
-            acc[NUO + 0] += p3 * z8r;
-            acc[NUO + 1] += p3 * z8i;
-            acc[NUO + 2] += q3 * z8r;
-            acc[NUO + 3] += q3 * z8i;
-            acc[NUO + 4] += p3 * z4r;
-            acc[NUO + 5] += p3 * z4i;
-            acc[NUO + 6] += q3 * z4r;
-            acc[NUO + 7] += q3 * z4i;
-            acc[NUO + 8] += ea * z4r;
-            acc[NUO + 9] += ea * z4i;
-            acc[NUO + 10] += eb * z4r;
-            acc[NUO + 11] += eb * z4i;
-            acc[NUO + 12] += ea;
-            acc[NUO + 13] += eb;
-            acc[NUO + 14] += vw * val[FV];
-          }
-        };
-
-        // ---- walk the annulus: row groups of 64, one row per lane
-        for (int rg = 0; rg < nrows; rg += 64) {
-          int s1 = 0, t1 = 0, s2 = 0, t2 = 0;
-          {
-            const int cy = cy0 + rg + (int)lane;
-            if (rg + (int)lane < nrows) {
-              const double ylo = g.y0 + cy * g.h - dlt;
-              const double yhi = g.y0 + (cy + 1) * g.h + dlt;
-              const double dymin = fmax(0.0, fmax(ylo - yi, yi - yhi));
-              if (dymin < rout) {
-                const double hw = sqrt(rout * rout - dymin * dymin) + dlt;
-                int cx0 = (int)floor((xi - hw - g.x0) * g.inv_h);
-                int cx1 = (int)floor((xi + hw - g.x0) * g.inv_h);
-                cx0 = imax(cx0, 0);
-                cx1 = imin(cx1, g.ncx - 1);
-                if (cx0 <= cx1) {
-                  // cells entirely inside the inner circle are skipped
-                  const double dymax = fmax(fabs(ylo - yi), fabs(yhi - yi));
-                  int hx0 = cx1 + 1, hx1 = cx1;
-                  if (dymax < rin) {
-                    const double hwi = sqrt(rin * rin - dymax * dymax) - 2.0 * dlt;
-                    hx0 = (int)ceil((xi - hwi - g.x0) * g.inv_h + 1e-7);
-                    hx1 = (int)floor((xi + hwi - g.x0) * g.inv_h - 1e-7) - 1;
-                    hx0 = imax(hx0, cx0);
-                    hx1 = imin(hx1, cx1);
-                    if (hx0 > hx1) { hx0 = cx1 + 1; hx1 = cx1; }
-                  }
-                  const int32_t* cs = cat.cell_start + (int64_t)cy * g.ncx;
-                  s1 = cs[cx0];
-                  t1 = cs[hx0];
-                  s2 = cs[hx1 + 1];
-                  t2 = cs[cx1 + 1];
-                }
-              }
-            }
-          }
-          const int rend = imin(64, nrows - rg);
-          // Flat walk over the row segments in batches of 64 neighbours; the
-          // positions and weights of the next batch are loaded while the
-          // current one is binned (and possibly consumed).
-          auto find = [&](int k, int& sk, int& base, int& end) -> bool {
-            for (; k < 2 * rend; ++k) {
-              const int r = k >> 1;
-              const int sv = __builtin_amdgcn_readlane((k & 1) ? s2 : s1, r);
-              const int tv = __builtin_amdgcn_readlane((k & 1) ? t2 : t1, r);
-              if (sv < tv) {
-                sk = k;
-                base = sv;
-                end = tv;
-                return true;
-              }
-            }
-            return false;
-          };
-          auto fetch = [&](int bs, int en, double& px, double& py, T& pa, T& pb, T& pw) {
-            const int j = bs + (int)lane;
-            if (j < en) {
-              px = cat.x[j];
-              py = cat.y[j];
-              pa = (T)cat.fa[j];
-              pb = (T)cat.fb[j];
-              pw = (T)cat.fw[j];
-            }
-          };
-          int sk = 0, base = 0, end = 0;
-          bool have = find(0, sk, base, end);
-          double cx = 0.0, cy = 0.0;
-          T ca = T(0), cb = T(0), cw = T(0);
-          if (have) fetch(base, end, cx, cy, ca, cb, cw);
-          while (have) {
-            int nk = sk, nbase = base + 64, nend = end;
-            bool nhave = true;
-            if (nbase >= nend) nhave = find(sk + 1, nk, nbase, nend);
-            double nx = 0.0, ny = 0.0;
-            T na = T(0), nbv = T(0), nw = T(0);
-            if (nhave) fetch(nbase, nend, nx, ny, na, nbv, nw);
-
-            bool inb = false;
-            double dx = 0.0, dy = 0.0;
-            if (base + (int)lane < end) {
-              dx = cx - xi;
-              dy = cy - yi;
-              const double rr = r2_exact(dx, dy);
-              inb = (rr >= e2lo) && (rr < e2hi);
-            }
-            const unsigned long long m = __ballot(inb);
-            if (inb) {
-              const unsigned pos = (tail + rank_in_mask(m)) & (QCAP - 1);
-              q_dx[wv][pos] = (T)dx;
-              q_dy[wv][pos] = (T)dy;
-              q_va[wv][pos] = ca;
-              q_vb[wv][pos] = cb;
-              q_vw[wv][pos] = cw;
-            }
-            const unsigned nadd = (unsigned)__popcll(m);
-            tail += nadd;
-            cnt += (int)nadd;
-            if (tail - head >= 64) {
-              wave_sync();
-              consume(64u);
-              head += 64;
-              if (++nblk == FOLD) {
-                fold_all<T, NU, NM>(acc, mst, lane);
-#pragma unroll
-                for (int u = 0; u < NU; ++u) acc[u] = T(0);
-                nblk = 0;
-              }
-              wave_sync();
-            }
-            cx = nx; cy = ny; ca = na; cb = nbv; cw = nw;
-            sk = nk; base = nbase; end = nend; have = nhave;
-          }
+          ++xs;
         }
-        if (tail != head) {
-          wave_sync();
-          consume(tail - head);
-        }
-        fold_all<T, NU, NM>(acc, mst, lane);
-
-        // ---- epilogue: masters -> LDS -> record blocks of this pass
-#pragma unroll
-        for (int m = 0; m < NM; ++m) stage[wv][64 * m + lane] = mst[m];
-        wave_sync();
-        const double* S = stage[wv];
-        T* rec = reinterpret_cast<T*>(a.rec_aos);
-        float gmax = 0.f, wmax = 0.f;   // block maxima for the fp16 operand scaling
-        auto su = [&](int f, int k, int part) -> double {
-          if (k == 0 && part == 1) return 0.0;
-          return S[uidx(N, K0, f, k) + part];
-        };
-        for (int e = (int)lane; e < L.mpc; e += 64) {
-          double re = 0.0, im = 0.0;
-          bool mine = false;
-          if (e < L.offW) {                       // G_k
-            const int k = e - (2 * N + 3);
-            const int ko = k < 0 ? -k : k;
-            if (ko >= K0 && ko <= K1) {
-              mine = true;
-              const double ar = su(FA, ko, 0), ai = su(FA, ko, 1);
-              const double br = su(FB, ko, 0), bi = su(FB, ko, 1);
-              if (k >= 0) { re = ar - bi; im = ai + br; }
-              else        { re = ar + bi; im = br - ai; }
-            }
-          } else if (e < L.offQ) {                // W_k
-            const int k = e - L.offW - 2 * N;
-            const int ko = k < 0 ? -k : k;
-            if (ko >= K0 && ko <= K1) {
-              mine = true;
-              re = su(FW, ko, 0);
-              im = (k >= 0 ? 1.0 : -1.0) * su(FW, ko, 1);
-            }
-          } else if (e < L.offA) {                // Q_k
-            const int k = e - L.offQ + L.qlo;
-            const int ko = k < 0 ? -k : k;
-            if (ko >= K0 && ko <= K1) {
-              mine = true;
-              const double cr = su(FC, ko, 0), ci = su(FC, ko, 1);
-              const double dr = su(FD, ko, 0), di = su(FD, ko, 1);
-              if (k >= 0) { re = cr - di; im = ci + dr; }
-              else        { re = cr + di; im = dr - ci; }
-            }
-          } else if (e < L.offV) {                // A_k, k >= 0
-            const int k = e - L.offA;
-            if (k >= K0 && k <= K1) { mine = true; re = su(FE, k, 0); im = su(FE, k, 1); }
-          } else if (e < L.offS) {                // V_k, k >= 0
-            const int k = e - L.offV;
-            if (k >= K0 && k <= K1) { mine = true; re = su(FV, k, 0); im = su(FV, k, 1); }
-          } else if (P0) {                        // T_-8, T_-4, M_-4, M_0, U
-            const int sp = e - L.offS;
-            mine = true;
-            const double* X = S + NUO;
-            if (sp == S_T8)      { re = X[0] + X[3];  im = X[2] - X[1]; }
-            else if (sp == S_T4) { re = X[4] + X[7];  im = X[6] - X[5]; }
-            else if (sp == S_M4) { re = X[8] + X[11]; im = X[10] - X[9]; }
-            else if (sp == S_M0) { re = X[12];        im = X[13]; }
-            else                 { re = X[14];        im = 0.0; }
-          }
-          if (mine) {
-            const int64_t o = 2 * (((int64_t)idx * nb + b) * L.mpc + e);
-            rec[o] = (T)re;
-            rec[o + 1] = (T)im;
-            const float m = (float)fmax(fabs(re), fabs(im));
-            if (e < L.offW) gmax = fmaxf(gmax, m);
-            else if (e < L.offQ) wmax = fmaxf(wmax, m);
-          }
-        }
-        if (a.maxima != nullptr) {
-#pragma unroll
-          for (int d = 32; d >= 1; d >>= 1) {
-            gmax = fmaxf(gmax, __shfl_xor(gmax, d, 64));
-            wmax = fmaxf(wmax, __shfl_xor(wmax, d, 64));
-          }
-          if ((int)lane == b) {
-            lane_gmax = fmaxf(lane_gmax, gmax);
-            lane_wmax = fmaxf(lane_wmax, wmax);
-          }
-        }
-        if (P0 && b == 0 && lane == 0) {
-          // centre factors of this tile position
-          const double fa_i = cat.fa[i], fb_i = cat.fb[i], fw_i = cat.fw[i];
-          T* xg = reinterpret_cast<T*>(a.xg);
-          xg[2 * idx] = (T)fa_i;
-          xg[2 * idx + 1] = (T)fb_i;
-          reinterpret_cast<T*>(a.xw)[idx] = (T)fw_i;
-          lane_xmax = fmaxf(lane_xmax, (float)fmax(fabs(fa_i), fabs(fb_i)));
-          lane_wxmax = fmaxf(lane_wxmax, (float)fabs(fw_i));
-        }
-        if (P0) {
-          if (a.counts != nullptr && lane == 0) a.counts[(int64_t)idx * nb + b] = cnt;
-          wave_pairs += (unsigned long long)cnt;
-        }
-        wave_sync();
+        sh.cent[tc & 1] = idx;
       }
+    }
+    __syncthreads();
+    const int idx = __builtin_amdgcn_readfirstlane(sh.cent[tc & 1]);
+    ++tc;
+    if (idx < 0) break;
+    const int i = a.centres[idx];
+    const Gal<T> gi = gal[i];
+    const double xi = gi.x, yi = gi.y;
+
+    for (int b = 0; b < nb; ++b) {
+      const double e2lo = a.e2[b], e2hi = a.e2[b + 1];
+      // conservative culling radii and cell margin (binning itself is exact)
+      const double rin = a.edges[b] * (1.0 - 1e-9);
+      const double rout = a.edges[b + 1] * (1.0 + 1e-9);
+      const double dlt = 1e-9 * g.h;
+      int cy0 = (int)floor((yi - rout - g.y0) * g.inv_h) - 1;
+      int cy1 = (int)floor((yi + rout - g.y0) * g.inv_h) + 1;
+      cy0 = imax(cy0, 0);
+      cy1 = imin(cy1, g.ncy - 1);
+      const int nrows = cy1 - cy0 + 1;
+
+      T acc[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) acc[u] = T(0);
+      double mst[NM];
+#pragma unroll
+      for (int m = 0; m < NM; ++m) mst[m] = 0.0;
+      int nblk = 0;
+      int cnt = 0;
+      int carry_n = 0;
+      T c_dx = T(0), c_dy = T(0), c_a = T(0), c_b = T(0), c_w = T(0);
+
+      for (int rg = 0; rg < nrows; rg += 64) {
+        // ---- row table, one row per lane: segments [s1, s1 + l1) and
+        // [s2, s2 + l2) of the sorted catalogue (cells entirely inside the
+        // inner circle are skipped).  Wave 0 builds it and publishes it
+        // through LDS, so every wave walks the same list and takes the same
+        // number of barriers.
+        const unsigned tb = tt & 1u;
+        ++tt;
+        if constexpr (P0) {
+          int s1 = 0, l1 = 0, s2 = 0, l2 = 0;
+          const int cy = cy0 + rg + (int)lane;
+          if (rg + (int)lane < nrows) {
+            const double ylo = g.y0 + cy * g.h - dlt;
+            const double yhi = g.y0 + (cy + 1) * g.h + dlt;
+            const double dymin = fmax(0.0, fmax(ylo - yi, yi - yhi));
+            if (dymin < rout) {
+              const double hw = sqrt(rout * rout - dymin * dymin) + dlt;
+              int cx0 = (int)floor((xi - hw - g.x0) * g.inv_h);
+              int cx1 = (int)floor((xi + hw - g.x0) * g.inv_h);
+              cx0 = imax(cx0, 0);
+              cx1 = imin(cx1, g.ncx - 1);
+              if (cx0 <= cx1) {
+                const double dymax = fmax(fabs(ylo - yi), fabs(yhi - yi));
+                int hx0 = cx1 + 1, hx1 = cx1;
+                if (dymax < rin) {
+                  const double hwi = sqrt(rin * rin - dymax * dymax) - 2.0 * dlt;
+                  hx0 = (int)ceil((xi - hwi - g.x0) * g.inv_h + 1e-7);
+                  hx1 = (int)floor((xi + hwi - g.x0) * g.inv_h - 1e-7) - 1;
+                  hx0 = imax(hx0, cx0);
+                  hx1 = imin(hx1, cx1);
+                  if (hx0 > hx1) { hx0 = cx1 + 1; hx1 = cx1; }
+                }
+                const int32_t* cs = a.cat.cell_start + (int64_t)cy * g.ncx;
+                s1 = cs[cx0];
+                l1 = cs[hx0] - s1;
+                s2 = cs[hx1 + 1];
+                l2 = cs[cx1 + 1] - s2;
+              }
+            }
+          }
+          const int rl0 = l1 + l2;
+          int pe0 = rl0;   // inclusive prefix over rows
+#pragma unroll
+          for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(pe0, d, 64);
+            if ((int)lane >= d) pe0 += t;
+          }
+          sh.rows[tb][0][lane] = s1;
+          sh.rows[tb][1][lane] = l1;
+          sh.rows[tb][2][lane] = s2;
+          sh.rows[tb][3][lane] = rl0;
+          sh.rows[tb][4][lane] = pe0;
+        }
+        __syncthreads();
+        const int s1 = sh.rows[tb][0][lane];
+        const int l1 = sh.rows[tb][1][lane];
+        const int s2 = sh.rows[tb][2][lane];
+        const int rl = sh.rows[tb][3][lane];
+        const int pe = sh.rows[tb][4][lane];
+        const int ro = pe - rl;   // first flat index of this row
+        const int tot = __builtin_amdgcn_readlane(pe, 63);
+        const int nch = (tot + 63) >> 6;
+        const int rounds = (nch + W - 1) / W;
+
+        // sorted position of flat candidate 64 c + lane (-1 beyond the end)
+        auto locate = [&](int c) -> int {
+          const int f0 = c << 6;
+          const int f = f0 + (int)lane;
+          int j = -1;
+          unsigned long long m = __ballot(rl > 0 && ro < f0 + 64 && pe > f0);
+          while (m) {
+            const int r = __builtin_ctzll(m);
+            m &= m - 1;
+            const int orr = __builtin_amdgcn_readlane(ro, r);
+            const int rlr = __builtin_amdgcn_readlane(rl, r);
+            const int l1r = __builtin_amdgcn_readlane(l1, r);
+            const int s1r = __builtin_amdgcn_readlane(s1, r);
+            const int s2r = __builtin_amdgcn_readlane(s2, r);
+            const int off = f - orr;
+            if (off >= 0 && off < rlr) j = off < l1r ? s1r + off : s2r + (off - l1r);
+          }
+          return j;
+        };
+
+        Gal<T> gn{};
+        bool vn = false;
+        if (PASS < nch) {
+          const int j = locate(PASS);
+          if (j >= 0) { gn = gal[j]; vn = true; }
+        }
+        for (int r = 0; r < rounds; ++r) {
+          // ---- bin this wave's chunk (binary64 r^2, no contraction)
+          const Gal<T> gc = gn;
+          const bool vc = vn;
+          bool inb = false;
+          double dx = 0.0, dy = 0.0;
+          if (vc) {
+            dx = gc.x - xi;
+            dy = gc.y - yi;
+            const double rr = r2_exact(dx, dy);
+            inb = (rr >= e2lo) && (rr < e2hi);
+          }
+          const unsigned long long mm = __ballot(inb);
+          const unsigned buf = rc & 1u;
+          if (inb) {
+            const unsigned pos = rank_in_mask(mm);
+            QE<T> e;
+            e.dx = (T)dx;
+            e.dy = (T)dy;
+            e.a = gc.a;
+            e.b = gc.b;
+            sh.q[buf][PASS][pos] = e;
+            sh.qw[buf][PASS][pos] = gc.w;
+          }
+          if (lane == 0) sh.cnt[buf][PASS] = (int)__popcll(mm);
+          // ---- load the next round's chunk while this round is consumed
+          {
+            const int cn = (r + 1) * W + PASS;
+            vn = false;
+            if (cn < nch) {
+              const int j = locate(cn);
+              if (j >= 0) { gn = gal[j]; vn = true; }
+            }
+          }
+          __syncthreads();
+          ++rc;
+          // ---- every pass adds the round's neighbours
+          int pre[W + 1];
+          pre[0] = 0;
+#pragma unroll
+          for (int w = 0; w < W; ++w) pre[w + 1] = pre[w] + __builtin_amdgcn_readfirstlane(sh.cnt[buf][w]);
+          const int total = carry_n + pre[W];
+          cnt += pre[W];
+          auto fetch = [&](int v, T& ex, T& ey, T& ea, T& eb, T& ew) {
+            const int u = v - carry_n;
+            int w = 0, base = 0;
+#pragma unroll
+            for (int k = 1; k < W; ++k)
+              if (u >= pre[k]) { w = k; base = pre[k]; }
+            const QE<T> q = sh.q[buf][w][u - base];
+            ex = q.dx;
+            ey = q.dy;
+            ea = q.a;
+            eb = q.b;
+            ew = sh.qw[buf][w][u - base];
+          };
+          int s0 = 0;
+          while (s0 + 64 <= total) {
+            const int v = s0 + (int)lane;
+            T ex = c_dx, ey = c_dy, ea = c_a, eb = c_b, ew = c_w;
+            if (v >= carry_n) fetch(v, ex, ey, ea, eb, ew);
+            add_pair<T, N, K0, K1, P0, NUO>(acc, true, ex, ey, ea, eb, ew);
+            s0 += 64;
+            if (++nblk == FOLD) {
+              fold_all<T, NU, NM>(acc, mst, lane);
+#pragma unroll
+              for (int u = 0; u < NU; ++u) acc[u] = T(0);
+              nblk = 0;
+            }
+          }
+          const int rem = total - s0;
+          if ((int)lane < rem) {
+            const int v = s0 + (int)lane;
+            if (v >= carry_n) fetch(v, c_dx, c_dy, c_a, c_b, c_w);
+          }
+          carry_n = rem;
+        }
+      }
+      if (carry_n > 0)
+        add_pair<T, N, K0, K1, P0, NUO>(acc, (int)lane < carry_n, c_dx, c_dy, c_a, c_b, c_w);
+      fold_all<T, NU, NM>(acc, mst, lane);
+
+      // ---- epilogue: masters -> LDS -> record blocks of this pass
+      double* S = sh.stage[PASS];
+#pragma unroll
+      for (int m = 0; m < NM; ++m) S[64 * m + lane] = mst[m];
+      wave_sync();
+      T* rec = reinterpret_cast<T*>(a.rec_aos);
+      float gmax = 0.f, wmax = 0.f;   // block maxima for the fp16 operand scaling
+      auto su = [&](int f, int k, int part) -> double {
+        if (k == 0 && part == 1) return 0.0;
+        return S[uidx(N, K0, f, k) + part];
+      };
+      for (int e = (int)lane; e < L.mpc; e += 64) {
+        double re = 0.0, im = 0.0;
+        bool mine = false;
+        if (e < L.offW) {                       // G_k
+          const int k = e - (2 * N + 3);
+          const int ko = k < 0 ? -k : k;
+          if (ko >= K0 && ko <= K1) {
+            mine = true;
+            const double ar = su(FA, ko, 0), ai = su(FA, ko, 1);
+            const double br = su(FB, ko, 0), bi = su(FB, ko, 1);
+            if (k >= 0) { re = ar - bi; im = ai + br; }
+            else        { re = ar + bi; im = br - ai; }
+          }
+        } else if (e < L.offQ) {                // W_k
+          const int k = e - L.offW - 2 * N;
+          const int ko = k < 0 ? -k : k;
+          if (ko >= K0 && ko <= K1) {
+            mine = true;
+            re = su(FW, ko, 0);
+            im = (k >= 0 ? 1.0 : -1.0) * su(FW, ko, 1);
+          }
+        } else if (e < L.offA) {                // Q_k
+          const int k = e - L.offQ + L.qlo;
+          const int ko = k < 0 ? -k : k;
+          if (ko >= K0 && ko <= K1) {
+            mine = true;
+            const double cr = su(FC, ko, 0), ci = su(FC, ko, 1);
+            const double dr = su(FD, ko, 0), di = su(FD, ko, 1);
+            if (k >= 0) { re = cr - di; im = ci + dr; }
+            else        { re = cr + di; im = dr - ci; }
+          }
+        } else if (e < L.offV) {                // A_k, k >= 0
+          const int k = e - L.offA;
+          if (k >= K0 && k <= K1) { mine = true; re = su(FE, k, 0); im = su(FE, k, 1); }
+        } else if (e < L.offS) {                // V_k, k >= 0
+          const int k = e - L.offV;
+          if (k >= K0 && k <= K1) { mine = true; re = su(FV, k, 0); im = su(FV, k, 1); }
+        } else if (P0) {                        // T_-8, T_-4, M_-4, M_0, U
+          const int sp = e - L.offS;
+          mine = true;
+          const double* X = S + NUO;
+          if (sp == S_T8)      { re = X[0] + X[3];  im = X[2] - X[1]; }
+          else if (sp == S_T4) { re = X[4] + X[7];  im = X[6] - X[5]; }
+          else if (sp == S_M4) { re = X[8] + X[11]; im = X[10] - X[9]; }
+          else if (sp == S_M0) { re = X[12];        im = X[13]; }
+          else                 { re = X[14];        im = 0.0; }
+        }
+        if (mine) {
+          const int64_t o = 2 * (((int64_t)idx * nb + b) * L.mpc + e);
+          rec[o] = (T)re;
+          rec[o + 1] = (T)im;
+          const float mx = (float)fmax(fabs(re), fabs(im));
+          if (e < L.offW) gmax = fmaxf(gmax, mx);
+          else if (e < L.offQ) wmax = fmaxf(wmax, mx);
+        }
+      }
+      if (a.maxima != nullptr) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+          gmax = fmaxf(gmax, __shfl_xor(gmax, d, 64));
+          wmax = fmaxf(wmax, __shfl_xor(wmax, d, 64));
+        }
+        if ((int)lane == b) {
+          lane_gmax = fmaxf(lane_gmax, gmax);
+          lane_wmax = fmaxf(lane_wmax, wmax);
+        }
+      }
+      if (P0 && b == 0 && lane == 0) {
+        // centre factors of this tile position
+        T* xg = reinterpret_cast<T*>(a.xg);
+        xg[2 * idx] = gi.a;
+        xg[2 * idx + 1] = gi.b;
+        reinterpret_cast<T*>(a.xw)[idx] = gi.w;
+        lane_xmax = fmaxf(lane_xmax, (float)fmax(fabs((double)gi.a), fabs((double)gi.b)));
+        lane_wxmax = fmaxf(lane_wxmax, (float)fabs((double)gi.w));
+      }
+      if (P0) {
+        if (a.counts != nullptr && lane == 0) a.counts[(int64_t)idx * nb + b] = cnt;
+        wave_pairs += (unsigned long long)cnt;
+      }
+      wave_sync();
     }
   }
   if (P0 && a.pairs != nullptr && lane == 0 && wave_pairs) atomicAdd(a.pairs, wave_pairs);
@@ -613,16 +706,20 @@ __global__ __launch_bounds__(256) void stage_a_kernel(StageAArgs a) {
 }
 
 template <typename T, int N, int P>
-hipError_t launch_passes(const StageAArgs& a, hipStream_t s, int nblocks) {
-  constexpr int NP = plan_np(N, Budget<T>::units);
-  if constexpr (P < NP) {
-    hipLaunchKernelGGL((stage_a_kernel<T, N, P>), dim3(nblocks), dim3(256), 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_passes<T, N, P + 1>(a, s, nblocks);
-  } else {
-    return hipSuccess;
+__device__ __forceinline__ void dispatch(int wv, const StageAArgs& a,
+                                         Shared<T, Conf<T, N>::W, Conf<T, N>::NMX>& sh, unsigned lane) {
+  if constexpr (P < Conf<T, N>::W) {
+    if (wv == P) pass_body<T, N, P>(a, sh, lane);
+    else dispatch<T, N, P + 1>(wv, a, sh, lane);
   }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__((64 * Conf<T, N>::W)) void stage_a_kernel(StageAArgs a) {
+  __shared__ Shared<T, Conf<T, N>::W, Conf<T, N>::NMX> sh;
+  // wave index as a scalar, so each wave branches to its own pass only
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  dispatch<T, N, 0>(wv, a, sh, lane_id());
 }
 
 // [centre][bin][entry] (as written per centre) -> [entry][bin][centre],
@@ -661,19 +758,32 @@ __global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ sr
 }
 
 template <typename T, int N>
-hipError_t launch_n(const StageAArgs& a, hipStream_t s, int* npass) {
-  static_assert(plan_np(N, Budget<T>::units) <= 16, "too many passes");
-  *npass = plan_np(N, Budget<T>::units);
-  int nblocks = (a.ncent + 3) / 4;
+hipError_t launch_n(const StageAArgs& a, hipStream_t s, int* nlaunch) {
+  constexpr int W = Conf<T, N>::W;
+  // persistent workgroups: as many as are resident at once, a multiple of
+  // the 8 XCDs (blocks are dealt round-robin to the XCDs)
+  static int resident = -1;
+  if (resident < 0) {
+    int per_cu = 0, dev = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_a_kernel<T, N>, 64 * W, 0) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+      ncu = 256;
+    resident = per_cu * ncu;
+  }
+  int nblocks = a.ncent < resident ? a.ncent : resident;
   nblocks = ((nblocks + 7) / 8) * 8;
-  if (nblocks > 2048) nblocks = 2048;
   if (nblocks < 8) nblocks = 8;
-  hipError_t e = launch_passes<T, N, 0>(a, s, nblocks);
+  hipLaunchKernelGGL((stage_a_kernel<T, N>), dim3(nblocks), dim3(64 * W), 0, s, a);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int mpc = make_layout(N).mpc;
   const dim3 grid((a.ncent + 63) / 64, a.nb, (mpc + 63) / 64);
   hipLaunchKernelGGL(transpose_kernel<T>, grid, dim3(256), 0, s, reinterpret_cast<const T*>(a.rec_aos),
                      reinterpret_cast<T*>(a.rec), a.ncent, a.nb, mpc, a.ldc);
+  *nlaunch = 1;
   return hipGetLastError();
 }
 
@@ -697,9 +807,9 @@ FPCF4_DECL_N(15) FPCF4_DECL_N(16)
 }  // namespace sa
 
 template <typename T>
-hipError_t launch_stage_a(int nmax, const StageAArgs& a, hipStream_t s, int* npass) {
+hipError_t launch_stage_a(int nmax, const StageAArgs& a, hipStream_t s, int* nlaunch) {
   switch (nmax) {
-#define FPCF4_CASE(NN) case NN: return sa::launch_n<T, NN>(a, s, npass);
+#define FPCF4_CASE(NN) case NN: return sa::launch_n<T, NN>(a, s, nlaunch);
     FPCF4_CASE(0) FPCF4_CASE(1) FPCF4_CASE(2) FPCF4_CASE(3) FPCF4_CASE(4)
     FPCF4_CASE(5) FPCF4_CASE(6) FPCF4_CASE(7) FPCF4_CASE(8) FPCF4_CASE(9)
     FPCF4_CASE(10) FPCF4_CASE(11) FPCF4_CASE(12) FPCF4_CASE(13) FPCF4_CASE(14)
