@@ -324,6 +324,9 @@ template <typename T, int N> struct Conf {
   static constexpr PassPlan PP = pass_plan(N, Budget<T>::units);
   static constexpr int W = PP.np;        // waves per workgroup = passes
   static constexpr int NMX = max_blocks64(PP);
+  // waves per SIMD the register allocation aims at (binary32 passes fit 168
+  // VGPRs, three waves per SIMD; binary64 passes take two)
+  static constexpr int EU = sizeof(T) == 4 ? 3 : 2;
   static_assert(W >= 1 && W <= 16, "passes must fit one workgroup");
 };
 
@@ -715,7 +718,7 @@ __device__ __forceinline__ void dispatch(int wv, const StageAArgs& a,
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__((64 * Conf<T, N>::W)) void stage_a_kernel(StageAArgs a) {
+__global__ __launch_bounds__((64 * Conf<T, N>::W)) __attribute__((amdgpu_waves_per_eu(Conf<T, N>::EU))) void stage_a_kernel(StageAArgs a) {
   __shared__ Shared<T, Conf<T, N>::W, Conf<T, N>::NMX> sh;
   // wave index as a scalar, so each wave branches to its own pass only
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
