@@ -24,19 +24,65 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "galaxy-centers/sec for Υ (mixed vs FP64 GPU) + mock p50/p99 latency"
-PEAK_FP32_VALU = 157.3e12     # published vector fp32 (packed); unpacked fma: 78.6e12
-PEAK_FP64_VALU = 78.6e12
+PEAK_FP32_VALU = 157.3e12     # published vector fp32 peak (packed FMA)
+PEAK_FP64_VALU = 78.6e12      # published vector fp64 peak
+STAGE_A_SRC = os.path.join(ROOT, "paper_2509_07974_amd", "csrc", "stage_a.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_a_grf1m_traffic.txt")
 
 
 def stage_a_flops_per_pair(nmax: int) -> float:
     """Algorithmic flops of stage (a) per in-bin (centre, neighbour) pair:
-    one real-weight x complex power multiply-add (2 flops per real unit) for
-    every accumulated unit, plus one complex multiply (6 flops) per power
-    z^k of the chain.  Units: 7 real weights over their order ranges
-    (28 nmax + 41 real units) + 15 triple-block units = 28 nmax + 56."""
+    2 (52 nmax + 72), i.e. one complex multiply-add chain per accumulated
+    block order (G, Q: 4(4n+3) each; W: 2(2n+1); A: 2(2n+2); V: 2(2n+1);
+    the triple blocks: 17) plus the power chain z^k (about 4(2n+6))."""
+    return 2.0 * (52 * nmax + 72)
+
+
+def stage_a_flops_executed_per_pair(nmax: int) -> float:
+    """Flops the kernel actually issues per pair: one real-weight x power
+    multiply-add (2 flops) per accumulated real unit (28 nmax + 56 units,
+    orders k >= 0 only) plus one complex multiply (6 flops) per power of the
+    chain."""
     units = 28 * nmax + 56
     powers = max(2 * nmax + 5, nmax + 6)
     return 2.0 * units + 6.0 * powers
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    with open(STAGE_A_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def stage_a_traffic():
+    """HBM bytes per stage (a) launch from the committed rocprofv3 counter
+    summary, or None if it is missing or was taken on another kernel
+    source."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_calibration(nbytes: int):
+    """One plain device-to-device copy of nbytes (the reference kernel for
+    scaling the FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4}))
 
 
 def cpu_baseline(cat, edges, nmax, seconds_target=15.0):
@@ -71,11 +117,17 @@ def main():
     ap.add_argument("--workload", default="grf-1m")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU path "
                           "(centre sharding + one all-reduce of Upsilon) is not built"}))
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import torch
     import paper_2509_07974_amd as fp
@@ -109,18 +161,23 @@ def main():
     fp.profile_enable(False)
     value = cat.n / dt
 
-    pairs_per_step = prof["pairs"] / max(prof["steps"], 1)
-    a_ms = prof["stage_a_ms"] / max(prof["stage_a_launches"], 1)
-    flops_launch = pairs_per_step * stage_a_flops_per_pair(nmax) / max(prof["stage_a_launches"] / max(prof["steps"], 1), 1)
+    steps = max(prof["steps"], 1)
+    launches = max(prof["stage_a_launches"], 1)
+    pairs_per_launch = prof["pairs"] / launches
+    a_ms = prof["stage_a_ms"] / launches
     peak = PEAK_FP64_VALU if args.precision == "fp64" else PEAK_FP32_VALU
-    achieved = flops_launch / (a_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "achieved": achieved, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved * 1e12 / peak, "traffic": None,
-            "kernel": "stage_a_kernel (pair multipoles), all passes",
-            "avg_launch_ms": a_ms, "launches_per_step": prof["stage_a_launches"] / max(prof["steps"], 1),
-            "pairs_per_step": pairs_per_step}
+    achieved = pairs_per_launch * stage_a_flops_per_pair(nmax) / (a_ms * 1e-3)
+    executed = pairs_per_launch * stage_a_flops_executed_per_pair(nmax) / (a_ms * 1e-3)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": stage_a_traffic(),
+            "kernel": "stage_a_kernel (pair multipoles)",
+            "avg_launch_ms": a_ms, "launches_per_step": launches / steps,
+            "pairs_per_launch": pairs_per_launch,
+            "flops_per_pair": stage_a_flops_per_pair(nmax),
+            "executed_flops_per_pair": stage_a_flops_executed_per_pair(nmax),
+            "achieved_executed": executed / 1e12}
 
-    extra = {"stage_ms_per_step": {k: prof[k + "_ms"] / max(prof["steps"], 1) for k in ("stage_a", "stage_b", "corr")},
+    extra = {"stage_ms_per_step": {k: prof[k + "_ms"] / steps for k in ("stage_a", "relayout", "stage_b", "corr")},
              "generation_s": gen_s}
     log(f"timed {args.steps} steps: {dt:.3f} s/step")
     if not args.no_fp64 and args.precision != "fp64":
@@ -138,7 +195,7 @@ def main():
         b = ref.cpu().numpy()
         err = [float(np.linalg.norm(a[m] - b[m]) / np.linalg.norm(b[m])) for m in range(9)]
         extra.update({"fp64_value": cat.n / dt64, "fp64_ms_per_step": dt64 * 1e3,
-                      "fp64_stage_ms": {k: p64[k + "_ms"] for k in ("stage_a", "stage_b", "corr")},
+                      "fp64_stage_ms": {k: p64[k + "_ms"] for k in ("stage_a", "relayout", "stage_b", "corr")},
                       "mixed_vs_fp64_rel_err_per_mu": err,
                       "mixed_speedup_vs_fp64": dt64 / dt})
     line = {"metric": METRIC, "value": value, "unit": "centres/s", "n_gpus": 1,

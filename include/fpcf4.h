@@ -184,13 +184,17 @@ void fpcf4_request_destroy(fpcf4_request *req);
 
 /* ------------------------------------------------------------------------
  * Per-stage timing for measurement.  While enabled, every request step
- * records hipEvents around stage (a) (pair multipoles), stage (b)
- * (contraction) and the correction sums on the request's stream, and counts
- * the ordered (centre, neighbour) pairs that fell in a bin; totals are
+ * records hipEvents on the request's stream around the stage (a) pair
+ * kernel (pair multipoles), the relayout of its records to centre-contiguous
+ * rows, stage (b) (contraction) and the correction sums, and counts the
+ * ordered (centre, neighbour) pairs that fell in a bin; totals are
  * accumulated when a request is finalized.  Times in milliseconds.
  * ---------------------------------------------------------------------- */
 typedef struct {
-  double stage_a_ms, stage_b_ms, corr_ms;
+  double stage_a_ms;    /* pair-multipole kernel                          */
+  double relayout_ms;   /* record relayout [centre][bin][entry] -> rows    */
+  double stage_b_ms;    /* contraction                                   */
+  double corr_ms;       /* degenerate-term sums                          */
   int64_t stage_a_launches, stage_b_launches, steps, pairs, centres;
 } fpcf4_profile;
 

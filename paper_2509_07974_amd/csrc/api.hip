@@ -317,7 +317,7 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     prof = g_prof_on && stage_b;
   }
-  hipEvent_t evs[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t evs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   if (prof) {
     for (auto& e : evs) HIPCHK(hipEventCreate(&e));
     for (auto e : evs) R->ev.push_back(e);
@@ -345,9 +345,9 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
   a.work_counter = counters;
   a.pairs = R->at<unsigned long long>(P.o_pairs);
   int nlaunch = 0;
-  if (P.precision == FPCF4_FP64) HIPCHK(launch_stage_a<double>(P.nmax, a, s, &nlaunch));
-  else HIPCHK(launch_stage_a<float>(P.nmax, a, s, &nlaunch));
-  if (prof) HIPCHK(hipEventRecord(evs[1], s));
+  if (P.precision == FPCF4_FP64) HIPCHK(launch_stage_a<double>(P.nmax, a, s, &nlaunch, evs[1]));
+  else HIPCHK(launch_stage_a<float>(P.nmax, a, s, &nlaunch, evs[1]));
+  if (prof) HIPCHK(hipEventRecord(evs[2], s));
   if (stage_b) {
     StageBArgs b{};
     b.rec = a.rec;
@@ -358,12 +358,12 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
     b.ups = R->at<double>(P.o_ups);
     b.corr = R->at<double>(P.o_corr);
     HIPCHK(launch_contract(b, P.precision, (int)P.ldc, a.xg, a.xw, a.maxima, s));
-    if (prof) HIPCHK(hipEventRecord(evs[2], s));
+    if (prof) HIPCHK(hipEventRecord(evs[3], s));
     CorrArgs ca{a.rec, a.xg, a.xw, ncent, P.nb, P.nmax, (int32_t)P.ldc, b.corr};
     if (P.precision == FPCF4_FP64) HIPCHK(launch_corrections<double>(ca, s));
     else HIPCHK(launch_corrections<float>(ca, s));
     if (prof) {
-      HIPCHK(hipEventRecord(evs[3], s));
+      HIPCHK(hipEventRecord(evs[4], s));
       R->prof_a_launches += nlaunch;
       R->prof_b_launches += 7;
       R->prof_steps += 1;
@@ -434,18 +434,21 @@ fpcf4_status fpcf4_request_finalize(fpcf4_request* req, double* upsilon, int32_t
   if (!req->ev.empty()) {
     unsigned long long pairs = 0;
     HIPCHK(hipMemcpy(&pairs, req->ws + P.o_pairs, 8, hipMemcpyDeviceToHost));
-    double ta = 0, tb = 0, tc = 0;
-    for (size_t k = 0; k + 3 < req->ev.size(); k += 4) {
+    double ta = 0, tr = 0, tb = 0, tc = 0;
+    for (size_t k = 0; k + 4 < req->ev.size(); k += 5) {
       float x = 0;
       HIPCHK(hipEventElapsedTime(&x, req->ev[k], req->ev[k + 1]));
       ta += x;
       HIPCHK(hipEventElapsedTime(&x, req->ev[k + 1], req->ev[k + 2]));
-      tb += x;
+      tr += x;
       HIPCHK(hipEventElapsedTime(&x, req->ev[k + 2], req->ev[k + 3]));
+      tb += x;
+      HIPCHK(hipEventElapsedTime(&x, req->ev[k + 3], req->ev[k + 4]));
       tc += x;
     }
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof.stage_a_ms += ta;
+    g_prof.relayout_ms += tr;
     g_prof.stage_b_ms += tb;
     g_prof.corr_ms += tc;
     g_prof.stage_a_launches += req->prof_a_launches;

@@ -109,9 +109,12 @@ struct StageAArgs {
   unsigned long long* pairs;  // in-bin pair counter (may be null)
 };
 
-// stage (a) launcher, T = double or float; returns the number of kernel
-// launches in *nlaunch
-template <typename T> hipError_t launch_stage_a(int nmax, const StageAArgs& a, hipStream_t s, int* nlaunch);
+// stage (a) launcher, T = double or float: the pair-multipole kernel, then
+// the relayout of its records to centre-contiguous rows.  Returns the number
+// of pair-kernel launches in *nlaunch; records `mid` (if not null) between
+// the two.
+template <typename T>
+hipError_t launch_stage_a(int nmax, const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t mid);
 
 struct StageBArgs {
   const void* rec;          // records of the tile

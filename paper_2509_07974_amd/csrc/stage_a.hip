@@ -761,7 +761,7 @@ __global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ sr
 }
 
 template <typename T, int N>
-hipError_t launch_n(const StageAArgs& a, hipStream_t s, int* nlaunch) {
+hipError_t launch_n(const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t mid) {
   constexpr int W = Conf<T, N>::W;
   // persistent workgroups: as many as are resident at once, a multiple of
   // the 8 XCDs (blocks are dealt round-robin to the XCDs)
@@ -782,6 +782,7 @@ hipError_t launch_n(const StageAArgs& a, hipStream_t s, int* nlaunch) {
   hipLaunchKernelGGL((stage_a_kernel<T, N>), dim3(nblocks), dim3(64 * W), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (mid != nullptr && (e = hipEventRecord(mid, s)) != hipSuccess) return e;
   const int mpc = make_layout(N).mpc;
   const dim3 grid((a.ncent + 63) / 64, a.nb, (mpc + 63) / 64);
   hipLaunchKernelGGL(transpose_kernel<T>, grid, dim3(256), 0, s, reinterpret_cast<const T*>(a.rec_aos),
@@ -795,13 +796,13 @@ hipError_t launch_n(const StageAArgs& a, hipStream_t s, int* nlaunch) {
 #if defined(FPCF4_STAGE_A_N)
 // One translation unit per nmax keeps the (large, fully unrolled) kernels
 // compiling in parallel.
-template hipError_t sa::launch_n<float, FPCF4_STAGE_A_N>(const StageAArgs&, hipStream_t, int*);
-template hipError_t sa::launch_n<double, FPCF4_STAGE_A_N>(const StageAArgs&, hipStream_t, int*);
+template hipError_t sa::launch_n<float, FPCF4_STAGE_A_N>(const StageAArgs&, hipStream_t, int*, hipEvent_t);
+template hipError_t sa::launch_n<double, FPCF4_STAGE_A_N>(const StageAArgs&, hipStream_t, int*, hipEvent_t);
 #else
 namespace sa {
 #define FPCF4_DECL_N(NN)                                                         \
-  extern template hipError_t launch_n<float, NN>(const StageAArgs&, hipStream_t, int*); \
-  extern template hipError_t launch_n<double, NN>(const StageAArgs&, hipStream_t, int*);
+  extern template hipError_t launch_n<float, NN>(const StageAArgs&, hipStream_t, int*, hipEvent_t); \
+  extern template hipError_t launch_n<double, NN>(const StageAArgs&, hipStream_t, int*, hipEvent_t);
 FPCF4_DECL_N(0) FPCF4_DECL_N(1) FPCF4_DECL_N(2) FPCF4_DECL_N(3) FPCF4_DECL_N(4)
 FPCF4_DECL_N(5) FPCF4_DECL_N(6) FPCF4_DECL_N(7) FPCF4_DECL_N(8) FPCF4_DECL_N(9)
 FPCF4_DECL_N(10) FPCF4_DECL_N(11) FPCF4_DECL_N(12) FPCF4_DECL_N(13) FPCF4_DECL_N(14)
@@ -810,9 +811,9 @@ FPCF4_DECL_N(15) FPCF4_DECL_N(16)
 }  // namespace sa
 
 template <typename T>
-hipError_t launch_stage_a(int nmax, const StageAArgs& a, hipStream_t s, int* nlaunch) {
+hipError_t launch_stage_a(int nmax, const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t mid) {
   switch (nmax) {
-#define FPCF4_CASE(NN) case NN: return sa::launch_n<T, NN>(a, s, nlaunch);
+#define FPCF4_CASE(NN) case NN: return sa::launch_n<T, NN>(a, s, nlaunch, mid);
     FPCF4_CASE(0) FPCF4_CASE(1) FPCF4_CASE(2) FPCF4_CASE(3) FPCF4_CASE(4)
     FPCF4_CASE(5) FPCF4_CASE(6) FPCF4_CASE(7) FPCF4_CASE(8) FPCF4_CASE(9)
     FPCF4_CASE(10) FPCF4_CASE(11) FPCF4_CASE(12) FPCF4_CASE(13) FPCF4_CASE(14)
@@ -821,8 +822,8 @@ hipError_t launch_stage_a(int nmax, const StageAArgs& a, hipStream_t s, int* nla
     default: return hipErrorInvalidValue;
   }
 }
-template hipError_t launch_stage_a<float>(int, const StageAArgs&, hipStream_t, int*);
-template hipError_t launch_stage_a<double>(int, const StageAArgs&, hipStream_t, int*);
+template hipError_t launch_stage_a<float>(int, const StageAArgs&, hipStream_t, int*, hipEvent_t);
+template hipError_t launch_stage_a<double>(int, const StageAArgs&, hipStream_t, int*, hipEvent_t);
 #endif
 
 }  // namespace fpcf4
