@@ -108,6 +108,66 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Mock request stream for the latency report: the first SERVE_REQUESTS
+# requests of the seeded stream (N log-uniform in [1e5, 2e6] scaled by
+# SERVE_N_SCALE, square patches of 4-100 deg^2, 8-16 log bins over 1-100',
+# nmax 8), Poisson arrivals at a fixed rate.
+SERVE_REQUESTS = 24
+SERVE_N_SCALE = 0.25
+SERVE_SEED = 77
+SERVE_LAMBDA = None      # requests/s; None = 0.7 / mean service time measured alone
+
+
+def serving_report(precision: str):
+    import paper_2509_07974_amd as fp
+    from paper_2509_07974_amd.serve import Job, Server, latency_stats
+    import synth
+    t = time.perf_counter()
+    reqs = synth.serving_requests(SERVE_REQUESTS, n_scale=SERVE_N_SCALE)
+    cats = [synth.make_request_catalogue(r) for r in reqs]
+    log(f"serving: generated {len(reqs)} request catalogues in {time.perf_counter() - t:.1f} s")
+
+    def jobs():
+        return [Job(r["rid"], *c.arrays(), synth.log_edges(1.0, 100.0, r["nbins"]), r["nmax"],
+                    precision=precision) for r, c in zip(reqs, cats)]
+
+    alone = jobs()
+    service = []
+    for j in alone:
+        srv = Server()
+        t = time.perf_counter()
+        srv.submit(j)
+        srv.drain()
+        service.append(time.perf_counter() - t)
+    log(f"serving: alone pass {sum(service):.1f} s")
+    lam = SERVE_LAMBDA if SERVE_LAMBDA else 0.7 / float(np.mean(service))
+    rng = np.random.default_rng(SERVE_SEED)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, len(reqs)))
+    arrivals -= arrivals[0]
+    mix = jobs()
+    for j, a in zip(mix, arrivals):
+        j.arrival = float(a)
+    srv = Server()
+    t = time.perf_counter()
+    srv.run(mix)
+    wall = time.perf_counter() - t
+    stats = latency_stats(mix)
+    equal = all(m.state == "done" and a.state == "done" and np.array_equal(m.result, a.result)
+                for m, a in zip(mix, alone))
+    centres = sum(j.n for j in mix if j.state == "done")
+    log(f"serving: mix pass {wall:.1f} s, p50 {stats['p50_s']:.3f} s, p99 {stats['p99_s']:.3f} s")
+    return {"requests": len(mix), "precision": precision, "lambda_per_s": lam,
+            "lambda_source": "fixed" if SERVE_LAMBDA else "0.7 / mean alone service time",
+            "p50_latency_s": stats["p50_s"], "p99_latency_s": stats["p99_s"],
+            "mean_latency_s": stats["mean_s"], "max_latency_s": stats["max_s"],
+            "service_alone_p50_s": float(np.median(service)), "service_alone_mean_s": float(np.mean(service)),
+            "wall_s": wall, "centres_per_s": centres / wall,
+            "hbm_budget_bytes": srv.budget, "peak_admitted_bytes": srv.peak_used,
+            "mix_equals_alone": bool(equal),
+            "stream": f"seeded requests 0..{len(mix) - 1} (seeds 1000+r), N scaled by {SERVE_N_SCALE}, "
+                      f"Poisson arrivals seed {SERVE_SEED}"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +177,7 @@ def main():
     ap.add_argument("--workload", default="grf-1m")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the mock request-stream latency report")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -206,6 +267,11 @@ def main():
             "config": {"workload": args.workload, "description": desc, "n_galaxies": cat.n,
                        "nbins": len(edges) - 1, "nmax": nmax, "precision": args.precision},
             "roofline": roof}
+    if not args.no_serving:
+        extra["serving"] = serving_report(args.precision)
+        line["latency"] = {"p50_s": extra["serving"]["p50_latency_s"],
+                           "p99_s": extra["serving"]["p99_latency_s"],
+                           "workload": "mock request stream, see extra.serving"}
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         line["cpu_baseline"] = cpu_baseline(cat, edges, nmax)
