@@ -112,7 +112,7 @@ def log(*a):
 # requests of the seeded stream (N log-uniform in [1e5, 2e6] scaled by
 # SERVE_N_SCALE, square patches of 4-100 deg^2, 8-16 log bins over 1-100',
 # nmax 8), Poisson arrivals at a fixed rate.
-SERVE_REQUESTS = 24
+SERVE_REQUESTS = 48
 SERVE_N_SCALE = 0.25
 SERVE_SEED = 77
 SERVE_LAMBDA = None      # requests/s; None = 0.7 / mean service time measured alone

@@ -267,23 +267,28 @@ __device__ __forceinline__ void cpow(T zr, T zi, T& pr, T& pi) {
   }
 }
 
-// Add one in-bin neighbour (separation dx, dy; weights a = w g1, b = w g2,
-// w) to the units of one pass.  Lanes with valid == false add nothing.
+// One in-bin neighbour as every pass consumes it: z = e^{i phi} and the
+// seven real weights (a = Re wg, b = Im wg, c = Re (wg)^2, d = Im (wg)^2,
+// e = |wg|^2, v = w^2, and w), formed once by the lane that binned it.
+template <typename T> struct alignas(16) Q4 { T x, y, z, w; };
+template <typename T> struct Nb {
+  T zr, zi, a, b, c, d, e, v, w;
+};
+
+// Add one neighbour to the units of one pass.  Lanes with valid == false
+// add nothing.
 template <typename T, int N, int K0, int K1, bool P0, int NUO>
-__device__ __forceinline__ void add_pair(T* acc, bool valid, T dx, T dy, T va, T vb, T vw) {
-  if (!valid) {
-    dx = T(0); dy = T(0); va = T(0); vb = T(0); vw = T(0);
-  }
+__device__ __forceinline__ void add_pair(T* acc, bool valid, Nb<T> q) {
+  if (!valid) q = Nb<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
   T val[NF];
-  val[FA] = va;
-  val[FB] = vb;
-  val[FC] = va * va - vb * vb;
-  val[FD] = T(2) * va * vb;
-  val[FW] = vw;
-  val[FE] = va * va + vb * vb;
-  val[FV] = vw * vw;
-  const T inv = valid ? rsq<T>(dx * dx + dy * dy) : T(0);
-  const T zr = dx * inv, zi = dy * inv;
+  val[FA] = q.a;
+  val[FB] = q.b;
+  val[FC] = q.c;
+  val[FD] = q.d;
+  val[FW] = q.w;
+  val[FE] = q.e;
+  val[FV] = q.v;
+  const T zr = q.zr, zi = q.zi;
   T pr, pi;
   cpow<T, K0>(zr, zi, pr, pi);
   acc_orders<T, N, K0, K1, K0>(acc, val, pr, pi, zr, zi);
@@ -293,9 +298,9 @@ __device__ __forceinline__ void add_pair(T* acc, bool valid, T dx, T dy, T va, T
     const T z2r = zr * zr - zi * zi, z2i = T(2) * zr * zi;
     const T z4r = z2r * z2r - z2i * z2i, z4i = T(2) * z2r * z2i;
     const T z8r = z4r * z4r - z4i * z4i, z8i = T(2) * z4r * z4i;
-    const T p3 = val[FC] * va - val[FD] * vb;   // Re (w g)^3
-    const T q3 = val[FC] * vb + val[FD] * va;   // Im (w g)^3
-    const T ea = val[FE] * va, eb = val[FE] * vb;
+    const T p3 = q.c * q.a - q.d * q.b;   // Re (w g)^3
+    const T q3 = q.c * q.b + q.d * q.a;   // Im (w g)^3
+    const T ea = q.e * q.a, eb = q.e * q.b;
     acc[NUO + 0] += p3 * z8r;
     acc[NUO + 1] += p3 * z8i;
     acc[NUO + 2] += q3 * z8r;
@@ -310,7 +315,7 @@ __device__ __forceinline__ void add_pair(T* acc, bool valid, T dx, T dy, T va, T
     acc[NUO + 11] += eb * z4i;
     acc[NUO + 12] += ea;
     acc[NUO + 13] += eb;
-    acc[NUO + 14] += vw * val[FV];
+    acc[NUO + 14] += q.w * q.v;
   }
 }
 
@@ -330,26 +335,35 @@ template <typename T, int N> struct Conf {
   static_assert(W >= 1 && W <= 16, "passes must fit one workgroup");
 };
 
-// In-bin neighbour handed from the binning lanes to every pass.
-template <typename T> struct alignas(16) QE { T dx, dy, a, b; };
+__host__ __device__ constexpr int ring_cap(int w) {
+  int c = 64;
+  while (c < 64 * (w + 1)) c *= 2;
+  return c;
+}
 
 template <typename T, int W, int NMX> struct Shared {
-  QE<T> q[2][W][64];        // round buffers: wave w's compacted in-bin neighbours
-  T qw[2][W][64];
+  static constexpr int CAP = ring_cap(W);
+  // ring of in-bin neighbours (z, a, b | c, d, e, v | w); the entries of a
+  // round are appended in wave order, so a batch is 64 consecutive slots
+  Q4<T> q0[CAP];
+  Q4<T> q1[CAP];
+  T qw[CAP];
   double stage[W][NMX * 64];  // per-wave epilogue staging of the binary64 sums
   int rows[2][5][64];       // row table: s1, l1, s2, row length, inclusive prefix
-  int cnt[2][W];            // in-bin count of each wave's chunk
+  int cnt[W];               // in-bin count of each wave's chunk in this round
   int cent[2];              // centre broadcast
 };
 
 // One wave = one pass (an order range of the accumulators).  The waves of a
 // workgroup share the walk: in every round wave w bins chunk (W r + w) of the
-// annulus' flat candidate list, compacts its in-bin neighbours into its slot
-// of the round buffer, and after one workgroup barrier every wave adds the
-// round's neighbours, in the fixed order (carry, wave 0, ..., wave W-1), to
-// its own units in full batches of 64; a remainder below 64 is carried in
-// registers into the next round.  The order is the same in every wave and
-// every run (no atomics), so results are reproducible bit for bit.
+// annulus' flat candidate list and forms z and the weights of its in-bin
+// neighbours; after a barrier the in-bin counts of all waves are known and
+// each wave appends its neighbours to the LDS ring at its prefix offset
+// (wave order); after a second barrier every wave adds all complete batches
+// of 64 ring slots to its own units.  A remainder below 64 stays in the ring
+// for the next round; the last one of a bin is added as a partial batch.
+// The order is the same in every wave and every run (no atomics), so
+// results are reproducible bit for bit.
 template <typename T, int N, int PASS>
 __device__ __forceinline__ void pass_body(const StageAArgs& a,
                                           Shared<T, Conf<T, N>::W, Conf<T, N>::NMX>& sh,
@@ -371,7 +385,13 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
 
   const int xcd0 = blockIdx.x & 7;
   int xs = 0;          // pass 0: XCD cursor of the centre grab
-  unsigned rc = 0;     // rounds so far (round-buffer parity)
+  constexpr unsigned CAP = Shared<T, W, Conf<T, N>::NMX>::CAP;
+  unsigned head = 0, tail = 0;   // ring: appended / consumed neighbours
+  auto fetch = [&](unsigned slot) -> Nb<T> {
+    const Q4<T> u = sh.q0[slot];
+    const Q4<T> v = sh.q1[slot];
+    return Nb<T>{u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w, sh.qw[slot]};
+  };
   unsigned tc = 0;     // centres so far (broadcast-slot parity)
   unsigned tt = 0;     // row tables so far (table parity)
   unsigned long long wave_pairs = 0;
@@ -426,8 +446,6 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
       for (int m = 0; m < NM; ++m) mst[m] = 0.0;
       int nblk = 0;
       int cnt = 0;
-      int carry_n = 0;
-      T c_dx = T(0), c_dy = T(0), c_a = T(0), c_b = T(0), c_w = T(0);
 
       for (int rg = 0; rg < nrows; rg += 64) {
         // ---- row table, one row per lane: segments [s1, s1 + l1) and
@@ -532,18 +550,7 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
             inb = (rr >= e2lo) && (rr < e2hi);
           }
           const unsigned long long mm = __ballot(inb);
-          const unsigned buf = rc & 1u;
-          if (inb) {
-            const unsigned pos = rank_in_mask(mm);
-            QE<T> e;
-            e.dx = (T)dx;
-            e.dy = (T)dy;
-            e.a = gc.a;
-            e.b = gc.b;
-            sh.q[buf][PASS][pos] = e;
-            sh.qw[buf][PASS][pos] = gc.w;
-          }
-          if (lane == 0) sh.cnt[buf][PASS] = (int)__popcll(mm);
+          if (lane == 0) sh.cnt[PASS] = (int)__popcll(mm);
           // ---- load the next round's chunk while this round is consumed
           {
             const int cn = (r + 1) * W + PASS;
@@ -554,34 +561,30 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
             }
           }
           __syncthreads();
-          ++rc;
-          // ---- every pass adds the round's neighbours
-          int pre[W + 1];
-          pre[0] = 0;
+          // ---- append this wave's in-bin neighbours at its prefix offset
+          int before = 0, added = 0;
 #pragma unroll
-          for (int w = 0; w < W; ++w) pre[w + 1] = pre[w] + __builtin_amdgcn_readfirstlane(sh.cnt[buf][w]);
-          const int total = carry_n + pre[W];
-          cnt += pre[W];
-          auto fetch = [&](int v, T& ex, T& ey, T& ea, T& eb, T& ew) {
-            const int u = v - carry_n;
-            int w = 0, base = 0;
-#pragma unroll
-            for (int k = 1; k < W; ++k)
-              if (u >= pre[k]) { w = k; base = pre[k]; }
-            const QE<T> q = sh.q[buf][w][u - base];
-            ex = q.dx;
-            ey = q.dy;
-            ea = q.a;
-            eb = q.b;
-            ew = sh.qw[buf][w][u - base];
-          };
-          int s0 = 0;
-          while (s0 + 64 <= total) {
-            const int v = s0 + (int)lane;
-            T ex = c_dx, ey = c_dy, ea = c_a, eb = c_b, ew = c_w;
-            if (v >= carry_n) fetch(v, ex, ey, ea, eb, ew);
-            add_pair<T, N, K0, K1, P0, NUO>(acc, true, ex, ey, ea, eb, ew);
-            s0 += 64;
+          for (int w = 0; w < W; ++w) {
+            const int cw = __builtin_amdgcn_readfirstlane(sh.cnt[w]);
+            if (w < PASS) before += cw;
+            added += cw;
+          }
+          if (inb) {
+            const unsigned slot = (head + (unsigned)before + rank_in_mask(mm)) & (CAP - 1);
+            const T ex = (T)dx, ey = (T)dy;
+            const T inv = rsq<T>(ex * ex + ey * ey);
+            const T va = gc.a, vb = gc.b, vw = gc.w;
+            sh.q0[slot] = Q4<T>{ex * inv, ey * inv, va, vb};
+            sh.q1[slot] = Q4<T>{va * va - vb * vb, T(2) * va * vb, va * va + vb * vb, vw * vw};
+            sh.qw[slot] = vw;
+          }
+          head += (unsigned)added;
+          cnt += added;
+          __syncthreads();
+          // ---- every pass adds the complete batches
+          while (head - tail >= 64u) {
+            add_pair<T, N, K0, K1, P0, NUO>(acc, true, fetch((tail + lane) & (CAP - 1)));
+            tail += 64u;
             if (++nblk == FOLD) {
               fold_all<T, NU, NM>(acc, mst, lane);
 #pragma unroll
@@ -589,16 +592,15 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
               nblk = 0;
             }
           }
-          const int rem = total - s0;
-          if ((int)lane < rem) {
-            const int v = s0 + (int)lane;
-            if (v >= carry_n) fetch(v, c_dx, c_dy, c_a, c_b, c_w);
-          }
-          carry_n = rem;
         }
       }
-      if (carry_n > 0)
-        add_pair<T, N, K0, K1, P0, NUO>(acc, (int)lane < carry_n, c_dx, c_dy, c_a, c_b, c_w);
+      if (head != tail) {
+        const bool valid = lane < head - tail;
+        Nb<T> q{};
+        if (valid) q = fetch((tail + lane) & (CAP - 1));
+        add_pair<T, N, K0, K1, P0, NUO>(acc, valid, q);
+        tail = head;
+      }
       fold_all<T, NU, NM>(acc, mst, lane);
 
       // ---- epilogue: masters -> LDS -> record blocks of this pass
