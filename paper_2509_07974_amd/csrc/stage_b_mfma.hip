@@ -66,10 +66,16 @@ static_assert(mu_factors(1).x == mu_factors(6).x && same_fac(mu_factors(1).A, mu
 
 constexpr int KC = 32;       // centres per LDS chunk (two fp16 MFMA K-steps)
 
-// row tiles (16 rows of (mu, re/im, b2)) and column tiles per wave (16
-// columns of (b1, b3), 4 waves) for a bin-count class NBC in {8, 12, 16}
+// row tiles (16 rows of (mu, re/im, b2)), waves per workgroup and column
+// tiles per wave (16 columns of (b1, b3), tile T = wave + WB t) for a
+// bin-count class NBC in {8, 12, 16}.  A wave skips a whole column tile
+// past the used ones (a wave-uniform branch); inside a tile the MFMA
+// sequence is straight-line.
 __host__ __device__ constexpr int mt_of(int nmu, int nbc) { return (nmu * 2 * nbc + 15) / 16; }
-__host__ __device__ constexpr int ntw_of(int nbc) { return ((nbc * nbc + 15) / 16 + 3) / 4; }
+__host__ __device__ constexpr int wb_of(int nbc) { return nbc == 16 ? 8 : 4; }
+__host__ __device__ constexpr int ntw_of(int nbc) {
+  return ((nbc * nbc + 15) / 16 + wb_of(nbc) - 1) / wb_of(nbc);
+}
 
 __device__ __forceinline__ int fac_entry_k(const Layout& L, const Fac& f, int k) {
   return f.fam == F_G ? eG(L, k) : eW(L, k);
@@ -116,7 +122,9 @@ __device__ __forceinline__ void split8v(const float (&v)[8], typename Half8<PREC
 #pragma unroll
     for (int q = 0; q < 8; q += 2) {
       const h2 hh = __builtin_amdgcn_cvt_pkrtz(v[q], v[q + 1]);
-      const h2 ll = __builtin_amdgcn_cvt_pkrtz(v[q] - (float)hh[0], v[q + 1] - (float)hh[1]);
+      // v - hi is exact in binary32 (one mixed-precision fma each)
+      const h2 ll = __builtin_amdgcn_cvt_pkrtz(__builtin_fmaf(-(float)hh[0], 1.0f, v[q]),
+                                               __builtin_fmaf(-(float)hh[1], 1.0f, v[q + 1]));
       hi[q] = (_Float16)hh[0];
       hi[q + 1] = (_Float16)hh[1];
       lo[q] = (_Float16)ll[0];
@@ -152,17 +160,17 @@ struct BArgs {
 // Values a thread stages for one chunk: X and Z for two (bin, centre) slots
 // and the Y column of up to two (row tile, lane) slots, held in registers
 // across the compute of the previous chunk (software pipelining).
-template <typename T>
+template <typename T, int NXS, int NYS>
 struct Prefetch {
-  C2<T> xc[2], av[2], cv[2];
-  C2<T> y[2][4];
+  C2<T> xc[NXS], av[NXS], cv[NXS];
+  C2<T> y[NYS][4];
 };
 
 // ---------------------------------------------------------------------------
 // mixed precision
 // ---------------------------------------------------------------------------
 template <int PREC, int G, int NBC>
-__global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
+__global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
   typedef typename Half8<PREC>::type H8;
   constexpr Group GR = group_of(G);
   constexpr MuFactors F0 = mu_factors(GR.mu[0]);
@@ -170,13 +178,17 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
   constexpr int MT = mt_of(GR.nmu, NBC);
   constexpr int NTW = ntw_of(NBC);
   constexpr int KS = KC / 16;          // fp16 K-steps (16 centres) per chunk
+  constexpr int WB = wb_of(NBC);       // waves per workgroup
+  constexpr int NT = 64 * WB;
+  constexpr int NXS = (NBC * KC + NT - 1) / NT;       // (bin, centre) staging slots per thread
+  constexpr int NYS = (KS * MT * 64 + NT - 1) / NT;   // Y operand slots per thread
   const int nb = a.s.nb, n = a.s.nmax, nn = 2 * n + 1;
   const Layout L = make_layout(n);
   const int n2 = (int)blockIdx.x / nn - n;
   const int n3 = (int)blockIdx.x % nn - n;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int mrows = GR.nmu * 2 * nb;
-  const int mt = (mrows + 15) >> 4;
   const int ncols = nb * nb;
   const int ntiles = (ncols + 15) >> 4;
   const int ncent = a.s.ncent;
@@ -216,13 +228,13 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
   // ---- staging: global -> registers (issue), registers -> LDS (commit)
   const C2<float>* xg = reinterpret_cast<const C2<float>*>(a.xg);
   const float* xw = reinterpret_cast<const float*>(a.xw);
-  Prefetch<float> pf;
-  // this thread's two Y slots (K-step, row tile, lane) and their row meaning
-  int y_ks[2], y_m[2], y_l[2], y_part[2], y_b2[2], y_row[2], y_cj[2];
-  bool y_ok[2], y_on[2];
+  Prefetch<float, NXS, NYS> pf;
+  // this thread's Y slots (K-step, row tile, lane) and their row meaning
+  int y_ks[NYS], y_m[NYS], y_l[NYS], y_part[NYS], y_b2[NYS], y_row[NYS], y_cj[NYS];
+  bool y_ok[NYS], y_on[NYS];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int q = tid + 256 * h;
+  for (int h = 0; h < NYS; ++h) {
+    const int q = tid + NT * h;
     y_ks[h] = q / (MT * 64);
     y_m[h] = (q / 64) % MT;
     y_l[h] = q & 63;
@@ -238,8 +250,8 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
   }
   auto issue = [&](int c0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int slot = tid + 256 * h;          // (bin, centre) slot of X and Z
+    for (int h = 0; h < NXS; ++h) {
+      const int slot = tid + NT * h;           // (bin, centre) slot of X and Z
       const int b = slot / KC, cc = slot % KC, c = c0 + cc;
       pf.xc[h] = {0.f, 0.f};
       pf.av[h] = {0.f, 0.f};
@@ -252,7 +264,7 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
       }
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NYS; ++h) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) pf.y[h][u] = {0.f, 0.f};
       if (y_ok[h]) {
@@ -266,8 +278,8 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
   };
   auto commit = [&](int buf) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int slot = tid + 256 * h;
+    for (int h = 0; h < NXS; ++h) {
+      const int slot = tid + NT * h;
       const int b = slot / KC, cc = slot % KC;
       if (b < nb) {
         C2<float> xc = pf.xc[h], av = pf.av[h], cv = pf.cv[h];
@@ -280,7 +292,7 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
       }
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NYS; ++h) {
       if (!y_on[h]) continue;
       float v[8];
       if (y_ok[h]) {
@@ -308,17 +320,16 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
   // per-lane column (b1, b3) of each of this wave's tiles; padding columns
   // read the zero row nb of the X buffer (nb < 16 whenever nb^2 % 16 != 0)
   int b1c[NTW], b3c[NTW];
-  bool colok[NTW], tok[NTW];
+  bool colok[NTW];
 #pragma unroll
   for (int t = 0; t < NTW; ++t) {
-    const int T = wv + 4 * t;
+    const int T = wv + WB * t;
     const int j = 16 * T + (lane & 15);
-    tok[t] = T < ntiles;
-    colok[t] = tok[t] && (j < ncols);
+    colok[t] = j < ncols;
     b1c[t] = colok[t] ? j / nb : (nb < 16 ? nb : 0);
     b3c[t] = colok[t] ? j % nb : 0;
   }
-  for (int z = tid; z < 2 * 16 * (KC + 1); z += 256) {
+  for (int z = tid; z < 2 * 16 * (KC + 1); z += NT) {
     const int bb = (z / (KC + 1)) % 16;
     if (bb >= nb) Xs[z / (16 * (KC + 1))][bb][z % (KC + 1)] = {0.f, 0.f};
   }
@@ -352,9 +363,13 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
         yl[m] = Ys[buf][ks][m][1][lane];
       }
       const int cb = 16 * ks + 4 * (lane >> 4);
+      // form the Khatri-Rao operand of one column tile, then issue its MFMAs
+      // product by product over the row tiles, so that consecutive MFMAs
+      // accumulate into different registers.  Row tiles past the used rows
+      // multiply zero Y rows.
 #pragma unroll
       for (int t = 0; t < NTW; ++t) {
-        if (!tok[t]) continue;
+        if (wv + WB * t >= ntiles) break;   // wave-uniform
         float v[8];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -366,12 +381,11 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
         H8 rh, rl;
         split8v<PREC>(v, rh, rl);
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
-          if (m < mt) {
-            acc[m][t] = mfma16<PREC>(yh[m], rh, acc[m][t]);
-            acc[m][t] = mfma16<PREC>(yh[m], rl, acc[m][t]);
-            acc[m][t] = mfma16<PREC>(yl[m], rh, acc[m][t]);
-          }
+        for (int m = 0; m < MT; ++m) acc[m][t] = mfma16<PREC>(yh[m], rh, acc[m][t]);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m][t] = mfma16<PREC>(yh[m], rl, acc[m][t]);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m][t] = mfma16<PREC>(yl[m], rh, acc[m][t]);
       }
     }
     if ((ch & 15) == 15 || !more) {       // fold fp32 into binary64 every 512 centres
@@ -395,7 +409,6 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
     const int b1 = b1c[t], b3 = b3c[t];
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-      if (m >= mt) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * m + 4 * (lane >> 4) + r;
@@ -414,19 +427,22 @@ __global__ __launch_bounds__(256) void contract_mixed_kernel(BArgs a) {
 // binary64
 // ---------------------------------------------------------------------------
 template <int G, int NBC>
-__global__ __launch_bounds__(256) void contract_f64_kernel(BArgs a) {
+__global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
   constexpr Group GR = group_of(G);
   constexpr MuFactors F0 = mu_factors(GR.mu[0]);
   constexpr MuFactors F1 = mu_factors(GR.mu[1]);
   constexpr int MT = mt_of(GR.nmu, NBC);
   constexpr int NTW = ntw_of(NBC);
+  constexpr int WB = wb_of(NBC);
+  constexpr int NT = 64 * WB;
+  constexpr int NXS = (NBC * KC + NT - 1) / NT;  // (bin, centre) staging slots per thread
   const int nb = a.s.nb, n = a.s.nmax, nn = 2 * n + 1;
   const Layout L = make_layout(n);
   const int n2 = (int)blockIdx.x / nn - n;
   const int n3 = (int)blockIdx.x % nn - n;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int mrows = GR.nmu * 2 * nb;
-  const int mt = (mrows + 15) >> 4;
   const int ncols = nb * nb;
   const int ntiles = (ncols + 15) >> 4;
   const int ncent = a.s.ncent;
@@ -445,11 +461,11 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(BArgs a) {
   const double* xw = reinterpret_cast<const double*>(a.xw);
   struct PF {
     C2<double> xc, av, cv, y0, y1;
-  } pf[2];
+  } pf[NXS];
   auto issue = [&](int c0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int slot = tid + 256 * h;
+    for (int h = 0; h < NXS; ++h) {
+      const int slot = tid + NT * h;
       const int b = slot / KC, cc = slot % KC, c = c0 + cc;
       pf[h].xc = pf[h].av = pf[h].cv = pf[h].y0 = pf[h].y1 = {0.0, 0.0};
       if (b < nb && c < ncent) {
@@ -464,8 +480,8 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(BArgs a) {
   };
   auto commit = [&](int buf) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int slot = tid + 256 * h;
+    for (int h = 0; h < NXS; ++h) {
+      const int slot = tid + NT * h;
       const int b = slot / KC, cc = slot % KC;
       if (b < nb) {
         C2<double> xc = pf[h].xc, av = pf[h].av, cv = pf[h].cv, y0 = pf[h].y0, y1 = pf[h].y1;
@@ -494,13 +510,12 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(BArgs a) {
     arow_b2[m] = rr % nb;
   }
   int b1c[NTW], b3c[NTW];
-  bool colok[NTW], tok[NTW];
+  bool colok[NTW];
 #pragma unroll
   for (int t = 0; t < NTW; ++t) {
-    const int T = wv + 4 * t;
+    const int T = wv + WB * t;
     const int j = 16 * T + (lane & 15);
-    tok[t] = T < ntiles;
-    colok[t] = tok[t] && (j < ncols);
+    colok[t] = j < ncols;
     b1c[t] = colok[t] ? j / nb : 0;
     b3c[t] = colok[t] ? j % nb : 0;
   }
@@ -533,14 +548,14 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(BArgs a) {
       }
 #pragma unroll
       for (int t = 0; t < NTW; ++t) {
-        if (!tok[t]) continue;
+        if (wv + WB * t >= ntiles) break;   // wave-uniform
         const C2<double> xv = Xs[buf][b1c[t]][cc];
         const C2<double> zv = Zs[buf][b3c[t]][cc];
         double bv = pk ? xv.r * zv.i + xv.i * zv.r : xv.r * zv.r - xv.i * zv.i;
         bv = colok[t] ? bv : 0.0;
 #pragma unroll
         for (int m = 0; m < MT; ++m)
-          if (m < mt) acc[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv, acc[m][t], 0, 0, 0);
+          acc[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv, acc[m][t], 0, 0, 0);
       }
     }
     if (more) commit(buf ^ 1);
@@ -554,7 +569,6 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(BArgs a) {
     const int b1 = b1c[t], b3 = b3c[t];
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-      if (m >= mt) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * m + 4 * r + (lane >> 4);
@@ -571,13 +585,13 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(BArgs a) {
 template <int G, int NBC>
 static void launch_group_nbc(const BArgs& a, int precision, hipStream_t s) {
   const int nn = 2 * a.s.nmax + 1;
-  const dim3 grid(nn * nn);
+  const dim3 grid(nn * nn), block(64 * wb_of(NBC));
   if (precision == FPCF4_FP64)
-    hipLaunchKernelGGL((contract_f64_kernel<G, NBC>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((contract_f64_kernel<G, NBC>), grid, block, 0, s, a);
   else if (precision == FPCF4_MIXED_FP16)
-    hipLaunchKernelGGL((contract_mixed_kernel<FPCF4_MIXED_FP16, G, NBC>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((contract_mixed_kernel<FPCF4_MIXED_FP16, G, NBC>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((contract_mixed_kernel<FPCF4_MIXED_BF16, G, NBC>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((contract_mixed_kernel<FPCF4_MIXED_BF16, G, NBC>), grid, block, 0, s, a);
 }
 
 template <int G>

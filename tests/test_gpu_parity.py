@@ -92,6 +92,24 @@ def test_centre_subset(fp):
         assert np.all(rel_per_mu(got, ref) < TOL[prec])
 
 
+@functools.lru_cache(None)
+def bins_case(nb):
+    cat = synth.uniform_catalogue(40 + nb, 900, 40.0)
+    edges = synth.log_edges(1.0, 25.0, nb)
+    return cat, edges, oracle.upsilon(*cat.arrays(), edges, 2)
+
+
+@pytest.mark.parametrize("nb", [1, 9, 13, 16])
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_bin_count_classes(fp, nb, prec):
+    # every bin-count class of the contraction (full and partially filled
+    # column and row tiles) against the oracle
+    cat, edges, ref = bins_case(nb)
+    got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, 2, precision=prec)
+    err = rel_per_mu(got, ref)
+    assert np.all(err < TOL[prec]), err
+
+
 def test_degenerate_inputs(fp):
     edges = np.array([1.0, 2.0, 4.0])
     z = np.zeros(0)
