@@ -85,14 +85,61 @@ __host__ __device__ constexpr PassPlan greedy(int n, int cap) {
   }
   return P;
 }
-// Fewest passes within the register budget, then the smallest cap that
-// still needs no more passes (balanced passes).
-__host__ __device__ constexpr PassPlan pass_plan(int n, int budget) {
-  const int np = greedy(n, budget).np;
-  int cap = (total_units(n) + np - 1) / np;
-  while (greedy(n, cap).np > np) ++cap;
-  return greedy(n, cap);
+// Exactly W passes with the smallest largest pass: the smallest cap that
+// needs at most W passes, then the largest passes split in two (at the
+// order that balances their halves) until there are W.
+__host__ __device__ constexpr PassPlan plan_exact(int n, int w) {
+  int cap = (total_units(n) + w - 1) / w;
+  while (greedy(n, cap).np > w) ++cap;
+  PassPlan P = greedy(n, cap);
+  while (P.np < w) {
+    int big = -1;
+    for (int p = 0; p < P.np; ++p)
+      if (P.k1[p] > P.k0[p] && (big < 0 || P.units[p] > P.units[big])) big = p;
+    if (big < 0) break;   // every pass is a single order
+    const int k0 = P.k0[big], k1 = P.k1[big];
+    int best = k0, bestmax = 1 << 30;
+    for (int split = k0; split < k1; ++split) {
+      int lo = (big == 0) ? NSPECIAL : 0, hi = 0;
+      for (int k = k0; k <= split; ++k) lo += units_at(n, k);
+      for (int k = split + 1; k <= k1; ++k) hi += units_at(n, k);
+      const int m = imax(lo, hi);
+      if (m < bestmax) { bestmax = m; best = split; }
+    }
+    for (int p = P.np; p > big + 1; --p) {
+      P.k0[p] = P.k0[p - 1];
+      P.k1[p] = P.k1[p - 1];
+      P.units[p] = P.units[p - 1];
+    }
+    int lo = (big == 0) ? NSPECIAL : 0, hi = 0;
+    for (int k = k0; k <= best; ++k) lo += units_at(n, k);
+    for (int k = best + 1; k <= k1; ++k) hi += units_at(n, k);
+    P.k1[big] = best;
+    P.units[big] = lo;
+    P.k0[big + 1] = best + 1;
+    P.k1[big + 1] = k1;
+    P.units[big + 1] = hi;
+    ++P.np;
+  }
+  return P;
 }
+__host__ __device__ constexpr int max_units(const PassPlan& P) {
+  int m = 0;
+  for (int p = 0; p < P.np; ++p) m = imax(m, P.units[p]);
+  return m;
+}
+// Waves per workgroup (one per pass): a power of two, so that two or more
+// workgroups tile the four SIMDs of a CU evenly.  Binary32: the fewest waves
+// whose passes fit 132 accumulators, at least four from nmax 5 on; binary64
+// (two registers per accumulator): passes of at most 72.
+__host__ __device__ constexpr int choose_waves(int n, bool fp64) {
+  const int lim = fp64 ? 72 : 132;
+  int w = 1;
+  while (w < 8 && max_units(plan_exact(n, w)) > lim) w *= 2;
+  if (!fp64 && n >= 5 && w < 4) w = 4;
+  return w;
+}
+
 __host__ __device__ constexpr int ubase(int n, int k0, int k) {
   int b = 0;
   for (int kk = k0; kk < k; ++kk) b += units_at(n, kk);
@@ -106,8 +153,8 @@ __host__ __device__ constexpr int uidx(int n, int k0, int f, int k) {
 }
 
 template <typename T> struct Budget;
-template <> struct Budget<float> { static constexpr int units = 96; static constexpr int fold = 32; };
-template <> struct Budget<double> { static constexpr int units = 48; static constexpr int fold = 1 << 30; };
+template <> struct Budget<float> { static constexpr int fold = 32; };
+template <> struct Budget<double> { static constexpr int fold = 1 << 30; };
 
 __device__ __forceinline__ double r2_exact(double dx, double dy) {
 #pragma clang fp contract(off)
@@ -326,13 +373,16 @@ __host__ __device__ constexpr int max_blocks64(const PassPlan& P) {
 }
 
 template <typename T, int N> struct Conf {
-  static constexpr PassPlan PP = pass_plan(N, Budget<T>::units);
-  static constexpr int W = PP.np;        // waves per workgroup = passes
+  static constexpr int W = choose_waves(N, sizeof(T) == 8);   // waves per workgroup = passes
+  static constexpr PassPlan PP = plan_exact(N, W);
   static constexpr int NMX = max_blocks64(PP);
-  // waves per SIMD the register allocation aims at (binary32 passes fit 168
-  // VGPRs, three waves per SIMD; binary64 passes take two)
-  static constexpr int EU = sizeof(T) == 4 ? 3 : 2;
-  static_assert(W >= 1 && W <= 16, "passes must fit one workgroup");
+  // waves per SIMD the register allocation aims at: binary32 passes of up
+  // to 96 accumulators fit 168 VGPRs (three waves per SIMD), larger ones and
+  // binary64 passes take two
+  static constexpr int EU = (sizeof(T) == 4 && max_units(PP) <= 96) ? 3 : 2;
+  static_assert(PP.np == W, "one pass per wave");
+  static_assert(W == 1 || W == 2 || W == 4 || W == 8, "power-of-two workgroups");
+  static_assert((4 * EU) % W == 0 || W % 4 == 0, "workgroups must tile the SIMDs");
 };
 
 __host__ __device__ constexpr int ring_cap(int w) {
