@@ -184,8 +184,9 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
   constexpr int NYS = (KS * MT * 64 + NT - 1) / NT;   // Y operand slots per thread
   const int nb = a.s.nb, n = a.s.nmax, nn = 2 * n + 1;
   const Layout L = make_layout(n);
-  const int n2 = (int)blockIdx.x / nn - n;
-  const int n3 = (int)blockIdx.x % nn - n;
+  const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const int n2 = lb / nn - n;
+  const int n3 = lb % nn - n;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int mrows = GR.nmu * 2 * nb;
@@ -438,8 +439,9 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
   constexpr int NXS = (NBC * KC + NT - 1) / NT;  // (bin, centre) staging slots per thread
   const int nb = a.s.nb, n = a.s.nmax, nn = 2 * n + 1;
   const Layout L = make_layout(n);
-  const int n2 = (int)blockIdx.x / nn - n;
-  const int n3 = (int)blockIdx.x % nn - n;
+  const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const int n2 = lb / nn - n;
+  const int n3 = lb % nn - n;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int mrows = GR.nmu * 2 * nb;
