@@ -66,16 +66,6 @@ __host__ __device__ inline int eA(const Layout& L, int k) { return L.offA + k; }
 __host__ __device__ inline int eV(const Layout& L, int k) { return L.offV + k; }
 enum { S_T8 = 0, S_T4 = 1, S_M4 = 2, S_M0 = 3, S_U = 4 };
 
-// Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
-// xcd_block() maps the hardware block index to a logical one such that each
-// XCD receives one contiguous range of logical blocks, so neighbouring
-// logical blocks (which read the same operand rows) share that XCD's L2.
-__device__ __forceinline__ int xcd_block(int b, int nblocks) {
-  const int q = nblocks >> 3, r = nblocks & 7;
-  const int x = b & 7, i = b >> 3;
-  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
-
 // Cell grid of the spatially sorted catalogue (row-major cells).
 struct Grid {
   double x0, y0, h, inv_h;

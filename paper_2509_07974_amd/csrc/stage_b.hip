@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   const int nb = a.nb, n = a.nmax, nn = 2 * n + 1, ns = 4 * n + 1;
   const Layout L = make_layout(n);
   const int per_mu = 2 * nn + ns + 1;
-  const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const int lb = (int)blockIdx.x;
   const int mu = lb / per_mu;
   int r = lb % per_mu;
   int kind, ord = 0;

@@ -184,7 +184,7 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
   constexpr int NYS = (KS * MT * 64 + NT - 1) / NT;   // Y operand slots per thread
   const int nb = a.s.nb, n = a.s.nmax, nn = 2 * n + 1;
   const Layout L = make_layout(n);
-  const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const int lb = (int)blockIdx.x;
   const int n2 = lb / nn - n;
   const int n3 = lb % nn - n;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
   constexpr int NXS = (NBC * KC + NT - 1) / NT;  // (bin, centre) staging slots per thread
   const int nb = a.s.nb, n = a.s.nmax, nn = 2 * n + 1;
   const Layout L = make_layout(n);
-  const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const int lb = (int)blockIdx.x;
   const int n2 = lb / nn - n;
   const int n3 = lb % nn - n;
   const int tid = threadIdx.x, lane = tid & 63;
