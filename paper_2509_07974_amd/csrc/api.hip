@@ -63,7 +63,7 @@ struct PlanInfo {
   size_t sort_tmp = 0;
   // persistent buffers
   size_t o_gal, o_cells, o_centres, o_e2, o_edges, o_counters, o_bbox, o_bad,
-      o_pairs, o_part, o_ups, o_corr, o_xg, o_xw, o_counts, o_aos, o_region;
+      o_pairs, o_part, o_ups, o_corr, o_cpart, o_xg, o_xw, o_counts, o_aos, o_region;
   size_t region = 0;           // records of one tile, or create-time temporaries
   // create-time temporaries inside the region
   size_t t_raw, t_key_a, t_key_b, t_idx_a, t_idx_b, t_inv, t_sort, t_cent64;
@@ -139,6 +139,7 @@ fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   P.o_part = take(256 * 4 * 8);
   P.o_ups = take((size_t)9 * P.nb * P.nb * P.nb * nn * nn * 16);
   P.o_corr = take(corr_elems(P.nb, P.nmax) * 16);
+  P.o_cpart = take(corr_elems(P.nb, P.nmax) * 16 * CORR_SLICES);
   P.o_xg = take((size_t)P.ldc * 2 * P.tsize);
   P.o_xw = take((size_t)P.ldc * P.tsize);
   P.o_aos = take((size_t)P.tile * rec_per_centre);
@@ -359,7 +360,8 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
     b.corr = R->at<double>(P.o_corr);
     HIPCHK(launch_contract(b, P.precision, (int)P.ldc, a.xg, a.xw, a.maxima, s));
     if (prof) HIPCHK(hipEventRecord(evs[3], s));
-    CorrArgs ca{a.rec, a.xg, a.xw, ncent, P.nb, P.nmax, (int32_t)P.ldc, b.corr};
+    CorrArgs ca{a.rec, a.xg, a.xw, ncent, P.nb, P.nmax, (int32_t)P.ldc, b.corr,
+                R->at<double>(P.o_cpart)};
     if (P.precision == FPCF4_FP64) HIPCHK(launch_corrections<double>(ca, s));
     else HIPCHK(launch_corrections<float>(ca, s));
     if (prof) {

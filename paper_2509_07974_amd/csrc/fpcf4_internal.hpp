@@ -131,8 +131,10 @@ struct CorrArgs {
   const void* xg;
   const void* xw;
   int32_t ncent, nb, nmax, ldc;
-  double* corr;
+  double* corr;             // correction sums, accumulated over tiles
+  double* part;             // [CORR_SLICES][corr_elems] per-slice partial sums
 };
+constexpr int CORR_SLICES = 8;   // centre slices of the correction sums
 
 // contraction on MFMA (precision: FPCF4_FP64 / _MIXED_FP16 / _MIXED_BF16)
 hipError_t launch_contract(const StageBArgs& sb, int precision, int ldc, const void* xg,

@@ -25,31 +25,6 @@ static __host__ __device__ inline int64_t corr_mu_elems(int nb, int n) {
 }
 size_t corr_elems(int nb, int nmax) { return (size_t)(9 * corr_mu_elems(nb, nmax)); }
 
-template <typename T>
-struct Rec {
-  const T* p;
-  int nb, ldc;
-  __device__ __forceinline__ cplx at(int e, int b, int c) const {
-    const T* q = p + 2 * (((int64_t)e * nb + b) * ldc + c);
-    return {(double)q[0], (double)q[1]};
-  }
-};
-
-// correction block (Q, A or V family) at order k, bin b, centre c
-template <typename T>
-__device__ __forceinline__ cplx corr_fam(const Rec<T>& R, const Layout& L, int fam, int k, int b, int c) {
-  if (fam == C_Q) return R.at(eQ(L, k), b, c);
-  const int e = fam == C_A ? eA(L, k < 0 ? -k : k) : eV(L, k < 0 ? -k : k);
-  const cplx v = R.at(e, b, c);
-  return k < 0 ? cconj(v) : v;
-}
-
-template <typename T>
-__device__ __forceinline__ cplx fac_val(const Rec<T>& R, const Layout& L, const Fac& f, int k, int b, int c) {
-  const cplx v = R.at(f.fam == F_G ? eG(L, k) : eW(L, k), b, c);
-  return f.conj ? cconj(v) : v;
-}
-
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int CKC = 32;   // centres per LDS chunk
 
@@ -58,7 +33,10 @@ constexpr int CKC = 32;   // centres per LDS chunk
 // done on v_mfma_f64_16x16x4_f64 with the complex product split into real
 // rows [[E_r, -E_i], [E_i, E_r]] and columns [F_r; F_i].  The triple term
 // (kind 3) is the same GEMM with F = 1 in column 0.  The four waves take
-// alternate K-steps of each LDS-staged chunk and are summed at the end.
+// alternate K-steps of each LDS-staged chunk and are summed at the end.  The
+// centres are cut into CORR_SLICES contiguous slices (blockIdx.y), each
+// written to its own binary64 partial buffer; corr_reduce_kernel adds the
+// slices in a fixed order, so the sums stay deterministic.
 template <typename T>
 __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   const int nb = a.nb, n = a.nmax, nn = 2 * n + 1, ns = 4 * n + 1;
@@ -75,7 +53,6 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const MuFactors F = mu_factors(mu);
   const MuCorr C = mu_corr(mu);
-  const Rec<T> R{reinterpret_cast<const T*>(a.rec), nb, a.ldc};
   const T* xg = reinterpret_cast<const T*>(a.xg);
   const T* xw = reinterpret_cast<const T*>(a.xw);
   // equal-bin block (Table 1) and the remaining factor, selected by value
@@ -89,43 +66,81 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   const int t_entry = L.offS + C.t;
   const int xkind = F.x;
   const int ncent = a.ncent;
+  const int nch_all = (ncent + CKC - 1) / CKC;
+  const int ch0 = (int)(((int64_t)nch_all * blockIdx.y) / gridDim.y);
+  const int ch1 = (int)(((int64_t)nch_all * (blockIdx.y + 1)) / gridDim.y);
 
   __shared__ cplx Es[2][16][CKC + 1];
   __shared__ cplx Fs[2][16][CKC + 1];
   __shared__ d4 red[4][2][64];
 
-  cplx pe[2], pf[2], px[2];
-  auto issue = [&](int c0) {
+  // Row pointers and conjugations of this thread's two (bin, centre) slots,
+  // resolved once: per chunk a slot is three plain loads at centre c.
+  int eidx, eflip;   // Table 1 block entry; conjugate (A, V at negative order)
+  if (kind == 3) {
+    eidx = t_entry;
+    eflip = 0;
+  } else if (ce_fam == C_Q) {
+    eidx = eQ(L, ke);
+    eflip = 0;
+  } else {
+    const int k = ke < 0 ? -ke : ke;
+    eidx = ce_fam == C_A ? eA(L, k) : eV(L, k);
+    eflip = ke < 0;
+  }
+  const T* rec = reinterpret_cast<const T*>(a.rec);
+  const T* pe_row[2];
+  const T* pf_row[2];
+  bool slot_ok[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int b = (tid + 256 * h) / CKC;
+    slot_ok[h] = b < nb;
+    const int bb = slot_ok[h] ? b : 0;
+    pe_row[h] = rec + 2 * (((int64_t)eidx * nb + bb) * a.ldc);
+    pf_row[h] = rec + 2 * (((int64_t)e_fo * nb + bb) * a.ldc);
+  }
+  const double fone = 1.0;   // kind 3: F = 1 in column 0
+
+  // Raw values of one chunk (two (bin, centre) slots per thread).  The loads
+  // are unconditional (centre clamped to the tile), so they stay in flight
+  // across the MFMAs of the current chunk; masking, conjugation and the
+  // conversion to binary64 happen in commit.
+  struct Regs {
+    T e[2][2], f[2][2], x[2][2], w[2];
+  };
+  Regs ra, rbf;   // two chunks in flight: loads are issued two chunks ahead
+  auto issue = [&](Regs& g, int c0) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int slot = tid + 256 * h;
-      const int b = slot / CKC, c = c0 + slot % CKC;
-      pe[h] = pf[h] = px[h] = {0.0, 0.0};
-      if (b < nb && c < ncent) {
-        if (xkind == X_W) px[h] = {(double)xw[c], 0.0};
-        else px[h] = {(double)xg[2 * c], (double)xg[2 * c + 1]};
-        if (kind == 3) {
-          pe[h] = R.at(t_entry, b, c);
-          pf[h] = {b == 0 ? 1.0 : 0.0, 0.0};
-        } else {
-          pe[h] = corr_fam(R, L, ce_fam, ke, b, c);
-          pf[h] = R.at(e_fo, b, c);
-        }
-      }
+      int c = c0 + (tid + 256 * h) % CKC;
+      c = c < ncent ? c : ncent - 1;
+      g.e[h][0] = pe_row[h][2 * c];
+      g.e[h][1] = pe_row[h][2 * c + 1];
+      g.f[h][0] = pf_row[h][2 * c];
+      g.f[h][1] = pf_row[h][2 * c + 1];
+      g.x[h][0] = xg[2 * c];
+      g.x[h][1] = xg[2 * c + 1];
+      g.w[h] = xw[c];
     }
   };
-  auto commit = [&](int buf) {
+  auto commit = [&](const Regs& g, int c0, int buf) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int slot = tid + 256 * h;
       const int b = slot / CKC, cc = slot % CKC;
-      if (b < nb) {
-        cplx x = px[h];
+      if (slot_ok[h]) {
+        const bool live = c0 + cc < ncent;
+        cplx x = xkind == X_W ? cplx{(double)g.w[h], 0.0} : cplx{(double)g.x[h][0], (double)g.x[h][1]};
         if (xkind == X_GC) x.i = -x.i;
-        cplx f = pf[h];
-        if (kind != 3 && fo_conj) f.i = -f.i;
-        Es[buf][b][cc] = cmul(x, pe[h]);
-        Fs[buf][b][cc] = f;
+        cplx e{(double)g.e[h][0], (double)g.e[h][1]};
+        if (eflip) e.i = -e.i;
+        cplx f{(double)g.f[h][0], (double)g.f[h][1]};
+        if (kind == 3) f = {b == 0 ? fone : 0.0, 0.0};
+        else if (fo_conj) f.i = -f.i;
+        const cplx ex = cmul(x, e);
+        Es[buf][b][cc] = live ? ex : cplx{0.0, 0.0};
+        Fs[buf][b][cc] = live ? f : cplx{0.0, 0.0};
       }
     }
   };
@@ -145,14 +160,7 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   const int kq = lane >> 4;   // K index within the 4-wide step: centre kq/2, part kq%2
   d4 acc[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
 
-  const int nchunks = (ncent + CKC - 1) / CKC;
-  issue(0);
-  commit(0);
-  __syncthreads();
-  for (int ch = 0; ch < nchunks; ++ch) {
-    const int buf = ch & 1;
-    const bool more = ch + 1 < nchunks;
-    if (more) issue((ch + 1) * CKC);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < CKC / 8; ++q) {         // this wave's K-steps: wv, wv+4, ...
       const int ks = wv + 4 * q;
@@ -166,14 +174,30 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
         acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[m], 0, 0, 0);
       }
     }
-    if (more) commit(buf ^ 1);
+  };
+
+  // chunk ch sits in LDS buffer (ch - ch0) & 1; the registers hold the next
+  // one or two chunks, so every load has two chunks of compute to land
+  issue(ra, ch0 * CKC);
+  commit(ra, ch0 * CKC, 0);
+  __syncthreads();
+  if (ch0 + 1 < ch1) issue(ra, (ch0 + 1) * CKC);
+  for (int ch = ch0; ch < ch1; ch += 2) {
+    if (ch + 2 < ch1) issue(rbf, (ch + 2) * CKC);
+    compute(0);
+    if (ch + 1 < ch1) commit(ra, (ch + 1) * CKC, 1);
+    __syncthreads();
+    if (ch + 1 >= ch1) break;
+    if (ch + 3 < ch1) issue(ra, (ch + 3) * CKC);
+    compute(1);
+    if (ch + 2 < ch1) commit(rbf, (ch + 2) * CKC, 0);
     __syncthreads();
   }
   red[wv][0][lane] = acc[0];
   red[wv][1][lane] = acc[1];
   __syncthreads();
   if (wv != 0) return;
-  double* out = a.corr + 2 * (int64_t)mu * corr_mu_elems(nb, n);
+  double* out = a.part + 2 * ((int64_t)(9 * blockIdx.y + mu) * corr_mu_elems(nb, n));
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
     const d4 v = red[0][m][lane] + red[1][m][lane] + red[2][m][lane] + red[3][m][lane];
@@ -187,9 +211,19 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
       else if (kind == 1) o = (int64_t)nb * nb * nn + ((int64_t)beq * nb + bo) * nn + (ord + n);
       else if (kind == 2) o = 2LL * nb * nb * nn + ((int64_t)bo * nb + beq) * ns + (ord + 2 * n);
       else o = 2LL * nb * nb * nn + (int64_t)nb * nb * ns + beq;
-      out[2 * o + part] += v[e];
+      out[2 * o + part] = v[e];
     }
   }
+}
+
+// corr += sum over slices of the partial sums, slice by slice
+__global__ void corr_reduce_kernel(const double* part, int64_t elems, double* corr) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= elems) return;
+  double v = corr[i];
+#pragma unroll
+  for (int sl = 0; sl < CORR_SLICES; ++sl) v += part[sl * elems + i];
+  corr[i] = v;
 }
 
 template <typename T>
@@ -197,7 +231,10 @@ hipError_t launch_corrections(const CorrArgs& a, hipStream_t s) {
   if (a.ncent <= 0) return hipSuccess;
   const int nn = 2 * a.nmax + 1, ns = 4 * a.nmax + 1;
   const int blocks = 9 * (2 * nn + ns + 1);
-  hipLaunchKernelGGL(corr_kernel<T>, dim3(blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(corr_kernel<T>, dim3(blocks, CORR_SLICES), dim3(256), 0, s, a);
+  const int64_t elems = 2 * (int64_t)corr_elems(a.nb, a.nmax);
+  hipLaunchKernelGGL(corr_reduce_kernel, dim3((int)((elems + 255) / 256)), dim3(256), 0, s,
+                     (const double*)a.part, elems, a.corr);
   return hipGetLastError();
 }
 template hipError_t launch_corrections<double>(const CorrArgs&, hipStream_t);

@@ -189,6 +189,10 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
   const int n3 = lb % nn - n;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // column tiles of this wave: T = wr + WB t.  When the tiles do not split
+  // evenly, the wave holding one more is rotated with the block index, so
+  // that co-resident workgroups put their longer waves on different SIMDs.
+  const int wr = (wv + (int)blockIdx.x) & (WB - 1);
   const int mrows = GR.nmu * 2 * nb;
   const int ncols = nb * nb;
   const int ntiles = (ncols + 15) >> 4;
@@ -324,7 +328,7 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
   bool colok[NTW];
 #pragma unroll
   for (int t = 0; t < NTW; ++t) {
-    const int T = wv + WB * t;
+    const int T = wr + WB * t;
     const int j = 16 * T + (lane & 15);
     colok[t] = j < ncols;
     b1c[t] = colok[t] ? j / nb : (nb < 16 ? nb : 0);
@@ -370,7 +374,7 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
       // multiply zero Y rows.
 #pragma unroll
       for (int t = 0; t < NTW; ++t) {
-        if (wv + WB * t >= ntiles) break;   // wave-uniform
+        if (wr + WB * t >= ntiles) break;   // wave-uniform
         float v[8];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -444,6 +448,10 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
   const int n3 = lb % nn - n;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // column tiles of this wave: T = wr + WB t.  When the tiles do not split
+  // evenly, the wave holding one more is rotated with the block index, so
+  // that co-resident workgroups put their longer waves on different SIMDs.
+  const int wr = (wv + (int)blockIdx.x) & (WB - 1);
   const int mrows = GR.nmu * 2 * nb;
   const int ncols = nb * nb;
   const int ntiles = (ncols + 15) >> 4;
@@ -515,7 +523,7 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
   bool colok[NTW];
 #pragma unroll
   for (int t = 0; t < NTW; ++t) {
-    const int T = wv + WB * t;
+    const int T = wr + WB * t;
     const int j = 16 * T + (lane & 15);
     colok[t] = j < ncols;
     b1c[t] = colok[t] ? j / nb : 0;
@@ -550,7 +558,7 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
       }
 #pragma unroll
       for (int t = 0; t < NTW; ++t) {
-        if (wv + WB * t >= ntiles) break;   // wave-uniform
+        if (wr + WB * t >= ntiles) break;   // wave-uniform
         const C2<double> xv = Xs[buf][b1c[t]][cc];
         const C2<double> zv = Zs[buf][b3c[t]][cc];
         double bv = pk ? xv.r * zv.i + xv.i * zv.r : xv.r * zv.r - xv.i * zv.i;
