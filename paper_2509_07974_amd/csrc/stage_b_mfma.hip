@@ -253,35 +253,29 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
     y_row[h] = (mi ? rowB1 : rowB0) * nb + y_b2[h];
     y_cj[h] = mi ? F1.B.conj : F0.B.conj;
   }
+  // Loads are unconditional (bin and centre clamped into the tile) so that
+  // they stay in flight across the MFMAs; commit masks what lies outside.
   auto issue = [&](int c0) {
 #pragma unroll
     for (int h = 0; h < NXS; ++h) {
       const int slot = tid + NT * h;           // (bin, centre) slot of X and Z
-      const int b = slot / KC, cc = slot % KC, c = c0 + cc;
-      pf.xc[h] = {0.f, 0.f};
-      pf.av[h] = {0.f, 0.f};
-      pf.cv[h] = {0.f, 0.f};
-      if (b < nb && c < ncent) {
-        if (F0.x == X_W) pf.xc[h] = {xw[c], 0.f};
-        else pf.xc[h] = xg[c];
-        pf.av[h] = ldrec(rec, (int64_t)rowA * nb + b, ldc, c);
-        pf.cv[h] = ldrec(rec, (int64_t)rowC * nb + b, ldc, c);
-      }
+      const int b = slot / KC, c = c0 + slot % KC;
+      const int bl = b < nb ? b : nb - 1, cl = c < ncent ? c : ncent - 1;
+      if (F0.x == X_W) pf.xc[h] = {xw[cl], 0.f};
+      else pf.xc[h] = xg[cl];
+      pf.av[h] = ldrec(rec, (int64_t)rowA * nb + bl, ldc, cl);
+      pf.cv[h] = ldrec(rec, (int64_t)rowC * nb + bl, ldc, cl);
     }
 #pragma unroll
     for (int h = 0; h < NYS; ++h) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) pf.y[h][u] = {0.f, 0.f};
-      if (y_ok[h]) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int c = c0 + 16 * y_ks[h] + 4 * (y_l[h] >> 4) + u;
-          if (c < ncent) pf.y[h][u] = ldrec(rec, (int64_t)y_row[h], ldc, c);
-        }
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + 16 * y_ks[h] + 4 * (y_l[h] >> 4) + u;
+        pf.y[h][u] = ldrec(rec, (int64_t)y_row[h], ldc, c < ncent ? c : ncent - 1);
       }
     }
   };
-  auto commit = [&](int buf) {
+  auto commit = [&](int c0, int buf) {
 #pragma unroll
     for (int h = 0; h < NXS; ++h) {
       const int slot = tid + NT * h;
@@ -291,7 +285,8 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
         if (F0.x == X_GC) xc.i = -xc.i;
         if (F0.A.conj) av.i = -av.i;
         if (F0.C.conj) cv.i = -cv.i;
-        const float sx = sc_lds[0][b], sz = sc_lds[2][b];
+        const bool live = c0 + cc < ncent;
+        const float sx = live ? sc_lds[0][b] : 0.f, sz = live ? sc_lds[2][b] : 0.f;
         Xs[buf][b][cc] = {(xc.r * av.r - xc.i * av.i) * sx, (xc.r * av.i + xc.i * av.r) * sx};
         Zs[buf][b][cc] = {cv.r * sz, cv.i * sz};
       }
@@ -307,6 +302,7 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
         for (int u = 0; u < 4; ++u) {
           C2<float> y = pf.y[h][u];
           if (y_cj[h]) y.i = -y.i;
+          if (c0 + 16 * y_ks[h] + 4 * (y_l[h] >> 4) + u >= ncent) y = {0.f, 0.f};
           // row part 0 (real out): [ y_r, -y_i ];  part 1 (imag out): [ y_i, y_r ]
           v[2 * u] = (part ? y.i : y.r) * sy;
           v[2 * u + 1] = (part ? y.r : -y.i) * sy;
@@ -353,7 +349,7 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
   const int nchunks = (ncent + KC - 1) / KC;
   __syncthreads();              // scales visible
   issue(0);
-  commit(0);
+  commit(0, 0);
   __syncthreads();
   for (int ch = 0; ch < nchunks; ++ch) {
     const int buf = ch & 1;
@@ -403,7 +399,7 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
           acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
         }
     }
-    if (more) commit(buf ^ 1);
+    if (more) commit((ch + 1) * KC, buf ^ 1);
     __syncthreads();
   }
 
@@ -472,29 +468,29 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
   struct PF {
     C2<double> xc, av, cv, y0, y1;
   } pf[NXS];
+  // unconditional loads (clamped into the tile), masked in commit
   auto issue = [&](int c0) {
 #pragma unroll
     for (int h = 0; h < NXS; ++h) {
       const int slot = tid + NT * h;
-      const int b = slot / KC, cc = slot % KC, c = c0 + cc;
-      pf[h].xc = pf[h].av = pf[h].cv = pf[h].y0 = pf[h].y1 = {0.0, 0.0};
-      if (b < nb && c < ncent) {
-        if (F0.x == X_W) pf[h].xc = {xw[c], 0.0};
-        else pf[h].xc = xg[c];
-        pf[h].av = ldrec(rec, (int64_t)rowA * nb + b, ldc, c);
-        pf[h].cv = ldrec(rec, (int64_t)rowC * nb + b, ldc, c);
-        pf[h].y0 = ldrec(rec, (int64_t)rowB0 * nb + b, ldc, c);
-        if (GR.nmu == 2) pf[h].y1 = ldrec(rec, (int64_t)rowB1 * nb + b, ldc, c);
-      }
+      const int b = slot / KC, c = c0 + slot % KC;
+      const int bl = b < nb ? b : nb - 1, cl = c < ncent ? c : ncent - 1;
+      if (F0.x == X_W) pf[h].xc = {xw[cl], 0.0};
+      else pf[h].xc = xg[cl];
+      pf[h].av = ldrec(rec, (int64_t)rowA * nb + bl, ldc, cl);
+      pf[h].cv = ldrec(rec, (int64_t)rowC * nb + bl, ldc, cl);
+      pf[h].y0 = ldrec(rec, (int64_t)rowB0 * nb + bl, ldc, cl);
+      if (GR.nmu == 2) pf[h].y1 = ldrec(rec, (int64_t)rowB1 * nb + bl, ldc, cl);
     }
   };
-  auto commit = [&](int buf) {
+  auto commit = [&](int c0, int buf) {
 #pragma unroll
     for (int h = 0; h < NXS; ++h) {
       const int slot = tid + NT * h;
       const int b = slot / KC, cc = slot % KC;
       if (b < nb) {
         C2<double> xc = pf[h].xc, av = pf[h].av, cv = pf[h].cv, y0 = pf[h].y0, y1 = pf[h].y1;
+        if (c0 + cc >= ncent) xc = av = cv = y0 = y1 = {0.0, 0.0};
         if (F0.x == X_GC) xc.i = -xc.i;
         if (F0.A.conj) av.i = -av.i;
         if (F0.C.conj) cv.i = -cv.i;
@@ -538,7 +534,7 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
   const int nchunks = (ncent + KC - 1) / KC;
   const int kq = lane >> 4;  // k within the K=4 step: (centre = kq/2, part = kq%2)
   issue(0);
-  commit(0);
+  commit(0, 0);
   __syncthreads();
   for (int ch = 0; ch < nchunks; ++ch) {
     const int buf = ch & 1;
@@ -568,7 +564,7 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
           acc[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv, acc[m][t], 0, 0, 0);
       }
     }
-    if (more) commit(buf ^ 1);
+    if (more) commit((ch + 1) * KC, buf ^ 1);
     __syncthreads();
   }
 
