@@ -111,11 +111,14 @@ def log(*a):
 # Mock request stream for the latency report: the first SERVE_REQUESTS
 # requests of the seeded stream (N log-uniform in [1e5, 2e6] scaled by
 # SERVE_N_SCALE, square patches of 4-100 deg^2, 8-16 log bins over 1-100',
-# nmax 8), Poisson arrivals at a fixed rate.
+# nmax 8), Poisson arrivals at a fixed rate.  The rate is about 0.7 of the
+# service rate of these requests served one at a time (mean alone service
+# time 0.31 s on one MI355X), fixed so that latencies stay comparable between
+# builds; None derives it from the alone pass of the run itself.
 SERVE_REQUESTS = 48
 SERVE_N_SCALE = 0.25
 SERVE_SEED = 77
-SERVE_LAMBDA = None      # requests/s; None = 0.7 / mean service time measured alone
+SERVE_LAMBDA = 2.25      # requests/s
 
 
 def serving_report(precision: str):
