@@ -68,6 +68,7 @@ enum { FPCF4_FP64 = 0, FPCF4_MIXED_FP16 = 1, FPCF4_MIXED_BF16 = 2 };
 
 #define FPCF4_NMAX_SUPPORTED 16   /* largest nmax compiled in              */
 #define FPCF4_NBINS_SUPPORTED 16  /* largest number of radial bins         */
+#define FPCF4_NMAX3_SUPPORTED 32  /* largest 3PCF multipole (2 x the above) */
 #define FPCF4_NCORR 9             /* Upsilon_0..7 and N                    */
 
 /* Catalogue: structure of arrays of length n, caller-owned, read-only.
@@ -115,6 +116,35 @@ fpcf4_status estimate_4pcf_multipoles(const fpcf4_catalogue *cat,
                                       const fpcf4_bins *bins,
                                       const fpcf4_options *opts,
                                       double *upsilon, int32_t out_mem);
+
+/* Number of complex128 elements of the 3PCF output: 5 * nbins^2 * (2 nmax + 1). */
+int64_t fpcf4_output3_elems(int32_t nbins, int32_t nmax);
+
+/* Shear 3PCF multipoles through the order-N construction of the appendix on
+ * N-th order shear statistics, at N = 3 (natural components Gamma_0..Gamma_3
+ * from the beta matrix, generalised x-projection zeta_0 = (phi_1 + phi_2)/2):
+ *   Upsilon_{mu,n}(T1, T2) = sum_i x_i F1 F2 with
+ *   mu 0: x = w g,  F1 = G_{n-3},         F2 = G_{-n-3};
+ *   mu 1: x = conj(w g), F1 = G_{n-1},    F2 = G_{-n-1};
+ *   mu 2: x = w g,  F1 = conj G_{-n-1},   F2 = G_{-n-3};
+ *   mu 3: x = w g,  F1 = G_{n-3},         F2 = conj G_{n-1};
+ *   N   : x = w,    F1 = W_n,             F2 = W_{-n}
+ * (the multipole formula as printed in that appendix, without the sign a
+ * product of three projected shears -gamma_c e^{-2i zeta} would carry).
+ * The blocks come from the stage (a) records of order ceil(nmax / 2), so the
+ * pair stage is shared with the 4PCF path.
+ * opts->nmax is the largest 3PCF multipole, 0 <= nmax <= FPCF4_NMAX3_SUPPORTED;
+ * opts->precision selects the stage (a) accumulation (the contraction is
+ * binary64 in every mode); subtract_degenerate = 1 removes the terms with
+ * the same neighbour in both slots (distinct triplets).
+ * upsilon3: caller-owned complex128 (re, im) array
+ *   [5][nbins][nbins][2nmax+1], index 0..3 = Upsilon_mu, 4 = N, n stored at
+ *   offset n + nmax; host or device memory as out_mem says.
+ * Errors as for estimate_4pcf_multipoles; FPCF4_E_UNSUPPORTED for nmax > 32. */
+fpcf4_status estimate_3pcf_multipoles(const fpcf4_catalogue *cat,
+                                      const fpcf4_bins *bins,
+                                      const fpcf4_options *opts,
+                                      double *upsilon3, int32_t out_mem);
 
 /* Stage (a) only, for parity checks (Sect. 3.1: the per-centre blocks G_n and
  * W_n "defined as in P24", read as G_k = sum_j w_j gamma_j e^{+ik phi_ij} and

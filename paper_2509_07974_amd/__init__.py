@@ -16,9 +16,9 @@ from . import _lib
 from ._lib import (FP64, MIXED_FP16, MIXED_BF16, MEM_HOST, MEM_DEVICE, NMAX_SUPPORTED,
                    NBINS_SUPPORTED, Fpcf4Error, check, lib)
 
-__all__ = ["estimate_4pcf_multipoles", "debug_multipoles", "to_natural", "plan", "Request",
+__all__ = ["estimate_4pcf_multipoles", "estimate_3pcf_multipoles", "debug_multipoles", "to_natural", "plan", "Request",
            "profile_enable", "profile_read",
-           "PRECISIONS", "Fpcf4Error", "output_shape", "lib", "version"]
+           "PRECISIONS", "Fpcf4Error", "output_shape", "output3_shape", "lib", "version"]
 
 PRECISIONS = {"fp64": FP64, "fp16": MIXED_FP16, "bf16": MIXED_BF16}
 
@@ -30,6 +30,10 @@ def version() -> str:
 def output_shape(nbins: int, nmax: int):
     nn = 2 * nmax + 1
     return (9, nbins, nbins, nbins, nn, nn)
+
+
+def output3_shape(nbins: int, nmax: int):
+    return (5, nbins, nbins, 2 * nmax + 1)
 
 
 def _is_torch_device(a) -> bool:
@@ -111,6 +115,25 @@ def estimate_4pcf_multipoles(x, y, g1, g2, w, edges, nmax: int, precision="fp64"
         return res
     res = out if out is not None else np.empty(shape, dtype=np.complex128)
     check(lib().estimate_4pcf_multipoles(*m.refs(), C.c_void_p(res.ctypes.data), MEM_HOST))
+    return res
+
+
+def estimate_3pcf_multipoles(x, y, g1, g2, w, edges, nmax: int, precision="fp64",
+                             subtract_degenerate: bool = True, centers=None,
+                             tile_centers: int = 0, stream=None, out=None):
+    """Shear 3PCF multipoles Upsilon_{mu,n}(T1,T2), mu = 0..3, and N (index 4)
+    as a complex128 array [5, nb, nb, 2nmax+1] (NumPy for host inputs, a
+    torch tensor on the inputs' device for device inputs).  nmax <= 32."""
+    m = _Marshal(x, y, g1, g2, w, edges, nmax, precision, subtract_degenerate, centers,
+                 tile_centers, stream)
+    shape = output3_shape(m.nbins, m.nmax)
+    if m.device:
+        import torch
+        res = out if out is not None else torch.empty(shape, dtype=torch.complex128, device=m.torch_device)
+        check(lib().estimate_3pcf_multipoles(*m.refs(), C.c_void_p(res.data_ptr()), MEM_DEVICE))
+        return res
+    res = out if out is not None else np.empty(shape, dtype=np.complex128)
+    check(lib().estimate_3pcf_multipoles(*m.refs(), C.c_void_p(res.ctypes.data), MEM_HOST))
     return res
 
 

@@ -11,6 +11,7 @@ OK, E_INVALID_ARG, E_UNSUPPORTED, E_OUT_OF_MEMORY, E_DEVICE, E_BUDGET, E_CANCELL
 MEM_HOST, MEM_DEVICE = 0, 1
 FP64, MIXED_FP16, MIXED_BF16 = 0, 1, 2
 NMAX_SUPPORTED = 16
+NMAX3_SUPPORTED = 32
 NBINS_SUPPORTED = 16
 
 STATUS_NAMES = {
@@ -95,6 +96,10 @@ def lib():
     L.fpcf4_profile_read.restype = C.c_int32
     L.fpcf4_output_elems.argtypes = [C.c_int32, C.c_int32]
     L.fpcf4_output_elems.restype = C.c_int64
+    L.estimate_3pcf_multipoles.argtypes = [P(Catalogue), P(Bins), P(Options), C.c_void_p, C.c_int32]
+    L.estimate_3pcf_multipoles.restype = C.c_int32
+    L.fpcf4_output3_elems.argtypes = [C.c_int32, C.c_int32]
+    L.fpcf4_output3_elems.restype = C.c_int64
     _lib = L
     return L
 
@@ -108,5 +113,5 @@ EXPORTED = [
     "estimate_4pcf_multipoles", "fpcf4_debug_multipoles", "fpcf4_to_natural", "fpcf4_plan",
     "fpcf4_request_create", "fpcf4_request_step", "fpcf4_request_finalize",
     "fpcf4_request_destroy", "fpcf4_last_error", "fpcf4_version", "fpcf4_output_elems",
-    "fpcf4_profile_enable", "fpcf4_profile_read",
+    "fpcf4_profile_enable", "fpcf4_profile_read", "estimate_3pcf_multipoles", "fpcf4_output3_elems",
 ]

@@ -57,13 +57,17 @@ constexpr size_t kTileRecordBudget = size_t(32) << 30;
 struct PlanInfo {
   int64_t n = 0, ncent = 0, tile = 0, ntiles = 0, ldc = 0;
   int nb = 0, nmax = 0, precision = 0, subtract = 1;
+  int order = 4;               // 4: shear 4PCF; 3: shear 3PCF from records of order nmax
+  int m3 = 0;                  // 3PCF: largest multipole (<= 2 nmax)
+  size_t ups_bytes = 0, corr_bytes = 0, acc3_bytes = 0;
   Layout L{};
   size_t tsize = 8;            // bytes per real in records
   int64_t ncell_cap = 0;
   size_t sort_tmp = 0;
   // persistent buffers
   size_t o_gal, o_cells, o_centres, o_e2, o_edges, o_counters, o_bbox, o_bad,
-      o_pairs, o_part, o_ups, o_corr, o_cpart, o_xg, o_xw, o_counts, o_aos, o_region;
+      o_pairs, o_part, o_ups, o_corr, o_cpart, o_acc3, o_part3, o_xg, o_xw, o_counts, o_aos,
+      o_region;
   size_t region = 0;           // records of one tile, or create-time temporaries
   // create-time temporaries inside the region
   size_t t_raw, t_key_a, t_key_b, t_idx_a, t_idx_b, t_inv, t_sort, t_cent64;
@@ -100,9 +104,11 @@ fpcf4_status validate_common(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
 }
 
 fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
-                       const fpcf4_options* opts, PlanInfo& P) {
+                       const fpcf4_options* opts, PlanInfo& P, int order = 4, int m3 = 0) {
   fpcf4_status st = validate_common(cat, bins, opts);
   if (st != FPCF4_OK) return st;
+  P.order = order;
+  P.m3 = m3;
   P.n = cat->n;
   P.nb = bins->nbins;
   P.nmax = opts->nmax;
@@ -137,9 +143,14 @@ fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   P.o_bad = take(16);
   P.o_pairs = take(16);
   P.o_part = take(256 * 4 * 8);
-  P.o_ups = take((size_t)9 * P.nb * P.nb * P.nb * nn * nn * 16);
-  P.o_corr = take(corr_elems(P.nb, P.nmax) * 16);
-  P.o_cpart = take(corr_elems(P.nb, P.nmax) * 16 * CORR_SLICES);
+  P.ups_bytes = order == 4 ? (size_t)9 * P.nb * P.nb * P.nb * nn * nn * 16 : 0;
+  P.corr_bytes = order == 4 ? corr_elems(P.nb, P.nmax) * 16 : 0;
+  P.acc3_bytes = order == 3 ? three_elems(P.nb, m3) * 16 : 0;
+  P.o_ups = take(P.ups_bytes);
+  P.o_corr = take(P.corr_bytes);
+  P.o_cpart = take(P.corr_bytes * CORR_SLICES);
+  P.o_acc3 = take(P.acc3_bytes);
+  P.o_part3 = take(P.acc3_bytes * THREE_SLICES);
   P.o_xg = take((size_t)P.ldc * 2 * P.tsize);
   P.o_xw = take((size_t)P.ldc * P.tsize);
   P.o_aos = take((size_t)P.tile * rec_per_centre);
@@ -202,9 +213,10 @@ struct fpcf4_request {
 namespace {
 
 fpcf4_status request_init(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
-                          const fpcf4_options* opts, void* wsp, size_t bytes, fpcf4_request* R) {
+                          const fpcf4_options* opts, void* wsp, size_t bytes, fpcf4_request* R,
+                          int order = 4, int m3 = 0) {
   PlanInfo& P = R->P;
-  fpcf4_status st = make_plan(cat, bins, opts, P);
+  fpcf4_status st = make_plan(cat, bins, opts, P, order, m3);
   if (st != FPCF4_OK) return st;
   if (!wsp) return fail(FPCF4_E_INVALID_ARG, "null workspace");
   if (reinterpret_cast<uintptr_t>(wsp) % ALIGN) return fail(FPCF4_E_INVALID_ARG, "workspace not 256-byte aligned");
@@ -214,7 +226,6 @@ fpcf4_status request_init(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   R->stepped.assign((size_t)P.ntiles, 0);
   hipStream_t s = R->stream;
   const int64_t n = P.n;
-  const int nn = 2 * P.nmax + 1;
 
   // centre subset: validate on the host
   std::vector<int64_t> hc;
@@ -231,8 +242,9 @@ fpcf4_status request_init(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   }
 
   HIPCHK(hipMemsetAsync(R->ws + P.o_pairs, 0, 16, s));
-  HIPCHK(hipMemsetAsync(R->ws + P.o_ups, 0, (size_t)9 * P.nb * P.nb * P.nb * nn * nn * 16, s));
-  HIPCHK(hipMemsetAsync(R->ws + P.o_corr, 0, corr_elems(P.nb, P.nmax) * 16, s));
+  if (P.ups_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_ups, 0, P.ups_bytes, s));
+  if (P.corr_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_corr, 0, P.corr_bytes, s));
+  if (P.acc3_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_acc3, 0, P.acc3_bytes, s));
   std::vector<double> e2(P.nb + 1);
   for (int b = 0; b <= P.nb; ++b) e2[b] = bins->edges[b] * bins->edges[b];
   HIPCHK(hipMemcpyAsync(R->ws + P.o_e2, e2.data(), e2.size() * 8, hipMemcpyHostToDevice, s));
@@ -349,7 +361,20 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
   if (P.precision == FPCF4_FP64) HIPCHK(launch_stage_a<double>(P.nmax, a, s, &nlaunch, evs[1]));
   else HIPCHK(launch_stage_a<float>(P.nmax, a, s, &nlaunch, evs[1]));
   if (prof) HIPCHK(hipEventRecord(evs[2], s));
-  if (stage_b) {
+  if (stage_b && P.order == 3) {
+    ThreeArgs t3{a.rec, a.xg, a.xw, ncent, P.nb, P.nmax, P.m3, 2 * P.m3 + 1, (int32_t)P.ldc,
+                 R->at<double>(P.o_part3), R->at<double>(P.o_acc3)};
+    if (P.precision == FPCF4_FP64) HIPCHK(launch_three<double>(t3, s));
+    else HIPCHK(launch_three<float>(t3, s));
+    if (prof) {
+      HIPCHK(hipEventRecord(evs[3], s));
+      HIPCHK(hipEventRecord(evs[4], s));
+      R->prof_a_launches += nlaunch;
+      R->prof_b_launches += 3;
+      R->prof_steps += 1;
+      R->prof_centres += ncent;
+    }
+  } else if (stage_b) {
     StageBArgs b{};
     b.rec = a.rec;
     b.centres = a.centres;
@@ -384,6 +409,11 @@ int64_t fpcf4_output_elems(int32_t nbins, int32_t nmax) {
   if (nbins < 0 || nmax < 0) return 0;
   const int64_t nn = 2 * (int64_t)nmax + 1;
   return 9 * (int64_t)nbins * nbins * nbins * nn * nn;
+}
+
+int64_t fpcf4_output3_elems(int32_t nbins, int32_t nmax) {
+  if (nbins < 0 || nmax < 0) return 0;
+  return 5 * (int64_t)nbins * nbins * (2 * (int64_t)nmax + 1);
 }
 
 const char* fpcf4_last_error(void) { return g_err.c_str(); }
@@ -427,11 +457,19 @@ fpcf4_status fpcf4_request_finalize(fpcf4_request* req, double* upsilon, int32_t
   for (size_t t = 0; t < req->stepped.size(); ++t)
     if (!req->stepped[t]) return fail(FPCF4_E_INVALID_ARG, "tile %zu not stepped", t);
   hipStream_t s = req->stream;
-  double* ups = req->at<double>(P.o_ups);
-  HIPCHK(launch_finalize(ups, req->at<double>(P.o_corr), P.nb, P.nmax, P.subtract, ups, s));
-  const size_t bytes = (size_t)fpcf4_output_elems(P.nb, P.nmax) * 16;
-  HIPCHK(hipMemcpyAsync(upsilon, ups, bytes,
-                        out_mem == FPCF4_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+  if (P.order == 3) {
+    // the slice partials are free once every tile is reduced: stage the host copy there
+    const size_t bytes = (size_t)fpcf4_output3_elems(P.nb, P.m3) * 16;
+    double* dst = out_mem == FPCF4_MEM_DEVICE ? upsilon : req->at<double>(P.o_part3);
+    HIPCHK(launch_finalize3(req->at<double>(P.o_acc3), P.nb, P.m3, P.subtract, dst, s));
+    if (out_mem == FPCF4_MEM_HOST) HIPCHK(hipMemcpyAsync(upsilon, dst, bytes, hipMemcpyDeviceToHost, s));
+  } else {
+    double* ups = req->at<double>(P.o_ups);
+    HIPCHK(launch_finalize(ups, req->at<double>(P.o_corr), P.nb, P.nmax, P.subtract, ups, s));
+    const size_t bytes = (size_t)fpcf4_output_elems(P.nb, P.nmax) * 16;
+    HIPCHK(hipMemcpyAsync(upsilon, ups, bytes,
+                          out_mem == FPCF4_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+  }
   HIPCHK(hipStreamSynchronize(s));
   if (!req->ev.empty()) {
     unsigned long long pairs = 0;
@@ -493,6 +531,35 @@ fpcf4_status estimate_4pcf_multipoles(const fpcf4_catalogue* cat, const fpcf4_bi
   for (int64_t t = 0; st == FPCF4_OK && t < P.ntiles; ++t) st = fpcf4_request_step(R, t);
   if (st == FPCF4_OK) st = fpcf4_request_finalize(R, upsilon, out_mem);
   fpcf4_request_destroy(R);
+  hipError_t e = hipFreeAsync(ws, s);
+  if (st == FPCF4_OK && e != hipSuccess) return fail(FPCF4_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));
+  return st;
+}
+
+fpcf4_status estimate_3pcf_multipoles(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
+                                      const fpcf4_options* opts, double* upsilon3, int32_t out_mem) {
+  if (!upsilon3 || !opts) return fail(FPCF4_E_INVALID_ARG, "null argument");
+  if (out_mem != FPCF4_MEM_HOST && out_mem != FPCF4_MEM_DEVICE) return fail(FPCF4_E_INVALID_ARG, "out_mem %d", out_mem);
+  if (opts->nmax < 0) return fail(FPCF4_E_INVALID_ARG, "nmax < 0");
+  if (opts->nmax > FPCF4_NMAX3_SUPPORTED)
+    return fail(FPCF4_E_UNSUPPORTED, "3PCF nmax %d > %d", opts->nmax, FPCF4_NMAX3_SUPPORTED);
+  // stage (a) records of order ceil(m/2) hold every block the 3PCF reads
+  const int m = opts->nmax;
+  fpcf4_options o = *opts;
+  o.nmax = (m + 1) / 2;
+  PlanInfo P;
+  fpcf4_status st = make_plan(cat, bins, &o, P, 3, m);
+  if (st != FPCF4_OK) return st;
+  setup_pool();
+  hipStream_t s = static_cast<hipStream_t>(o.stream);
+  void* ws = nullptr;
+  HIPCHK(hipMallocAsync(&ws, P.total, s));
+  fpcf4_request* R = new (std::nothrow) fpcf4_request();
+  if (!R) st = fail(FPCF4_E_OUT_OF_MEMORY, "host allocation failed");
+  if (st == FPCF4_OK) st = request_init(cat, bins, &o, ws, P.total, R, 3, m);
+  for (int64_t t = 0; st == FPCF4_OK && t < P.ntiles; ++t) st = request_step(R, t, true);
+  if (st == FPCF4_OK) st = fpcf4_request_finalize(R, upsilon3, out_mem);
+  delete R;
   hipError_t e = hipFreeAsync(ws, s);
   if (st == FPCF4_OK && e != hipSuccess) return fail(FPCF4_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));
   return st;

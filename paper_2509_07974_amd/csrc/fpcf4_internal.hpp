@@ -144,4 +144,24 @@ size_t corr_elems(int nb, int nmax);  // complex elements of the correction buff
 hipError_t launch_finalize(const double* ups_raw, const double* corr, int nb, int nmax,
                            int subtract, double* out, hipStream_t s);
 
+// Shear 3PCF multipoles from the same records (threepcf.hip).
+constexpr int THREE_SLICES = 16;   // centre slices of the 3PCF sums
+// complex elements of the 3PCF accumulator: [5][2m+1][nb][nb] multipole sums,
+// then [5][nb] same-neighbour sums
+__host__ __device__ inline size_t three_elems(int nb, int m) {
+  return (size_t)5 * (2 * m + 1) * nb * nb + (size_t)5 * nb;
+}
+struct ThreeArgs {
+  const void* rec;          // records of the tile (stage (a) of order n4)
+  const void* xg;           // [ldc] complex (T): w g of each tile centre
+  const void* xw;           // [ldc] (T): w of each tile centre
+  int32_t ncent, nb, n4, m, nn, ldc;   // m: largest 3PCF multipole (<= 2 n4), nn = 2m+1
+  double* part;             // [THREE_SLICES][three_elems] complex partial sums
+  double* acc;              // [three_elems] complex, accumulated over tiles
+};
+template <typename T> hipError_t launch_three(const ThreeArgs& a, hipStream_t s);
+// out[mu][b1][b2][n] (complex128) from the accumulator, minus the
+// same-neighbour sums on b1 == b2 when subtract != 0
+hipError_t launch_finalize3(const double* acc, int nb, int m, int subtract, double* out, hipStream_t s);
+
 }  // namespace fpcf4

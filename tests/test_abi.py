@@ -74,3 +74,38 @@ def test_python_binding_rejects_mismatched_lengths():
     with pytest.raises(ValueError):
         m.estimate_4pcf_multipoles(np.zeros(3), np.zeros(4), np.zeros(3), np.zeros(3), np.zeros(3),
                                    [1.0, 2.0], 1)
+
+
+def _call3(edges, nmax=2, n=10, precision=0):
+    from paper_2509_07974_amd import _lib
+    ensure_built()
+    rng = np.random.default_rng(0)
+    arrs = [rng.uniform(0, 10, n) for _ in range(5)]
+    cat = _lib.Catalogue(n, *[a.ctypes.data for a in arrs], _lib.MEM_HOST)
+    e = np.asarray(edges, dtype=np.float64)
+    bins = _lib.Bins(e.size - 1, e.ctypes.data)
+    opts = _lib.Options(nmax, precision, 1, 0, None, 0, 0, None)
+    out = np.zeros(max(1, 5 * (e.size - 1) ** 2 * (2 * max(nmax, 0) + 1)), complex)
+    st = _lib.lib().estimate_3pcf_multipoles(C.byref(cat), C.byref(bins), C.byref(opts),
+                                             C.c_void_p(out.ctypes.data), _lib.MEM_HOST)
+    return st, _lib.lib().fpcf4_last_error().decode()
+
+
+@pytest.mark.parametrize("edges,nmax,code", [
+    ([1.0, 0.5, 2.0], 4, -1),          # not increasing
+    ([0.0, 1.0, 2.0], 4, -1),          # edges[0] <= 0
+    ([1.0, 2.0], -1, -1),              # nmax < 0
+    ([1.0, 2.0], 33, -2),              # beyond the compiled 3PCF multipoles
+    (list(np.geomspace(1, 10, 18)), 2, -2),   # 17 bins > 16
+])
+def test_3pcf_invalid_arguments_rejected(edges, nmax, code):
+    st, msg = _call3(edges, nmax)
+    assert st == code and msg
+
+
+def test_3pcf_output_elems_and_null_output():
+    from paper_2509_07974_amd import _lib
+    lib = ensure_built()
+    assert lib.fpcf4_output3_elems(12, 10) == 5 * 144 * 21
+    assert lib.fpcf4_output3_elems(-1, 2) == 0
+    assert lib.estimate_3pcf_multipoles(None, None, None, None, 0) == _lib.E_INVALID_ARG
