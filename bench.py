@@ -171,6 +171,46 @@ def serving_report(precision: str):
                       f"Poisson arrivals seed {SERVE_SEED}"}
 
 
+THREEPCF_NMAX = 10   # 3PCF multipoles |n| <= 10 (stage (a) records of order 5)
+
+
+def threepcf_report(fp, dev, n, edges, precision, no_fp64):
+    """The shear 3PCF on the same catalogue: one warmup and two timed
+    estimates (per-stage times from the library's events), and the FP64 path
+    for the error per component."""
+    import torch
+
+    def run(prec):
+        return fp.estimate_3pcf_multipoles(*dev, edges, THREEPCF_NMAX, precision=prec)
+
+    run(precision)
+    torch.cuda.synchronize()
+    fp.profile_enable(True)
+    t = time.perf_counter()
+    for _ in range(2):
+        out = run(precision)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / 2
+    prof = fp.profile_read()
+    fp.profile_enable(False)
+    rep = {"nmax": THREEPCF_NMAX, "record_order": (THREEPCF_NMAX + 1) // 2, "precision": precision,
+           "value": n / dt, "unit": "centres/s", "ms_per_step": dt * 1e3,
+           "stage_ms_per_step": {"stage_a": prof["stage_a_ms"] / 2, "relayout": prof["relayout_ms"] / 2,
+                                 "contraction_and_same_neighbour": prof["stage_b_ms"] / 2}}
+    log(f"3pcf: {dt:.3f} s/step")
+    if not no_fp64 and precision != "fp64":
+        run("fp64")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ref = run("fp64")
+        torch.cuda.synchronize()
+        rep["fp64_ms_per_step"] = (time.perf_counter() - t) * 1e3
+        a, b = out.cpu().numpy(), ref.cpu().numpy()
+        rep["mixed_vs_fp64_rel_err_per_mu"] = [float(np.linalg.norm(a[m] - b[m]) / np.linalg.norm(b[m]))
+                                               for m in range(5)]
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,6 +221,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the mock request-stream latency report")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 mixed-path run")
+    ap.add_argument("--no-3pcf", action="store_true", help="skip the 3PCF run on the same catalogue")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -262,6 +304,21 @@ def main():
                       "fp64_stage_ms_per_step": {k: p64[k + "_ms"] for k in ("stage_a", "relayout", "stage_b", "corr")},
                       "mixed_vs_fp64_rel_err_per_mu": err,
                       "mixed_speedup_vs_fp64": dt64 / dt})
+        if not args.no_bf16 and args.precision != "bf16":
+            run("bf16")
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            o16 = run("bf16")
+            torch.cuda.synchronize()
+            dtb = time.perf_counter() - t
+            c = o16.cpu().numpy()
+            extra.update({"bf16_value": cat.n / dtb, "bf16_ms_per_step": dtb * 1e3,
+                          "bf16_vs_fp64_rel_err_per_mu":
+                              [float(np.linalg.norm(c[m] - b[m]) / np.linalg.norm(b[m])) for m in range(9)]})
+            log(f"bf16: {dtb:.3f} s/step")
+        del ref
+    if not args.no_3pcf:
+        extra["threepcf"] = threepcf_report(fp, dev, cat.n, edges, args.precision, args.no_fp64)
     line = {"metric": METRIC, "value": value, "unit": "centres/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

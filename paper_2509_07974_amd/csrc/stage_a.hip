@@ -318,15 +318,21 @@ __device__ __forceinline__ void cpow(T zr, T zi, T& pr, T& pi) {
 // seven real weights (a = Re wg, b = Im wg, c = Re (wg)^2, d = Im (wg)^2,
 // e = |wg|^2, v = w^2, and w), formed once by the lane that binned it.
 template <typename T> struct alignas(16) Q4 { T x, y, z, w; };
+template <typename T> struct alignas(2 * sizeof(T)) Q2 { T x, y; };
 template <typename T> struct Nb {
   T zr, zi, a, b, c, d, e, v, w;
+  T sr, si;   // z^K0 of the consuming pass, when the binning lane formed it
 };
+
+// binary32 passes take their first power z^K0 from the ring (formed once per
+// neighbour by the lane that binned it); binary64 rings would not fit LDS
+template <typename T> constexpr bool kRingStarts = sizeof(T) == 4;
 
 // Add one neighbour to the units of one pass.  Lanes with valid == false
 // add nothing.
 template <typename T, int N, int K0, int K1, bool P0, int NUO>
 __device__ __forceinline__ void add_pair(T* acc, bool valid, Nb<T> q) {
-  if (!valid) q = Nb<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+  if (!valid) q = Nb<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
   T val[NF];
   val[FA] = q.a;
   val[FB] = q.b;
@@ -337,7 +343,12 @@ __device__ __forceinline__ void add_pair(T* acc, bool valid, Nb<T> q) {
   val[FV] = q.v;
   const T zr = q.zr, zi = q.zi;
   T pr, pi;
-  cpow<T, K0>(zr, zi, pr, pi);
+  if constexpr (K0 > 0 && kRingStarts<T>) {
+    pr = q.sr;
+    pi = q.si;
+  } else {
+    cpow<T, K0>(zr, zi, pr, pi);
+  }
   acc_orders<T, N, K0, K1, K0>(acc, val, pr, pi, zr, zi);
   if constexpr (P0) {
     // triple-counting blocks: T_-8, T_-4 (weight (w g)^3), M_-4, M_0
@@ -398,11 +409,26 @@ template <typename T, int W, int NMX> struct Shared {
   Q4<T> q0[CAP];
   Q4<T> q1[CAP];
   T qw[CAP];
+  Q2<T> qk[kRingStarts<T> && W > 1 ? W - 1 : 1][kRingStarts<T> && W > 1 ? CAP : 1];  // z^K0 of passes 1..W-1
   double stage[W][NMX * 64];  // per-wave epilogue staging of the binary64 sums
   int rows[2][5][64];       // row table: s1, l1, s2, row length, inclusive prefix
   int cnt[W];               // in-bin count of each wave's chunk in this round
   int cent[2];              // centre broadcast
 };
+
+// First powers z^K0 of passes P..W-1, each the previous one times
+// z^(K0[P] - K0[P-1]), written to the ring slot of the neighbour.
+template <typename T, int N, int P, typename SH>
+__device__ __forceinline__ void put_starts(SH& sh, unsigned slot, T zr, T zi, T pr, T pi) {
+  if constexpr (P < Conf<T, N>::W) {
+    constexpr int D = Conf<T, N>::PP.k0[P] - Conf<T, N>::PP.k0[P - 1];
+    T dr, di;
+    cpow<T, D>(zr, zi, dr, di);
+    const T nr = pr * dr - pi * di, ni = pr * di + pi * dr;
+    sh.qk[P - 1][slot] = Q2<T>{nr, ni};
+    put_starts<T, N, P + 1>(sh, slot, zr, zi, nr, ni);
+  }
+}
 
 // One wave = one pass (an order range of the accumulators).  The waves of a
 // workgroup share the walk: in every round wave w bins chunk (W r + w) of the
@@ -440,7 +466,13 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
   auto fetch = [&](unsigned slot) -> Nb<T> {
     const Q4<T> u = sh.q0[slot];
     const Q4<T> v = sh.q1[slot];
-    return Nb<T>{u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w, sh.qw[slot]};
+    T sr = T(0), si = T(0);
+    if constexpr (PASS > 0 && kRingStarts<T>) {
+      const Q2<T> k = sh.qk[PASS - 1][slot];
+      sr = k.x;
+      si = k.y;
+    }
+    return Nb<T>{u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w, sh.qw[slot], sr, si};
   };
   unsigned tc = 0;     // centres so far (broadcast-slot parity)
   unsigned tt = 0;     // row tables so far (table parity)
@@ -624,7 +656,9 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
             const T ex = (T)dx, ey = (T)dy;
             const T inv = rsq<T>(ex * ex + ey * ey);
             const T va = gc.a, vb = gc.b, vw = gc.w;
-            sh.q0[slot] = Q4<T>{ex * inv, ey * inv, va, vb};
+            const T zr = ex * inv, zi = ey * inv;
+            sh.q0[slot] = Q4<T>{zr, zi, va, vb};
+            if constexpr (kRingStarts<T> && W > 1) put_starts<T, N, 1>(sh, slot, zr, zi, T(1), T(0));
             sh.q1[slot] = Q4<T>{va * va - vb * vb, T(2) * va * vb, va * va + vb * vb, vw * vw};
             sh.qw[slot] = vw;
           }
