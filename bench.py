@@ -26,6 +26,8 @@ sys.path.insert(0, ROOT)
 METRIC = "galaxy-centers/sec for Υ (mixed vs FP64 GPU) + mock p50/p99 latency"
 PEAK_FP32_VALU = 157.3e12     # published vector fp32 peak (packed FMA)
 PEAK_FP64_VALU = 78.6e12      # published vector fp64 peak
+PEAK_F16_MFMA = 2.5e15        # published dense fp16 / bf16 matrix peak
+PEAK_FP64_MFMA = 78.6e12      # published fp64 matrix peak
 STAGE_A_SRC = os.path.join(ROOT, "paper_2509_07974_amd", "csrc", "stage_a.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_a_grf1m_traffic.txt")
 
@@ -121,13 +123,18 @@ SERVE_SEED = 77
 SERVE_LAMBDA = 2.25      # requests/s
 
 
-def serving_report(precision: str):
+def serving_report(precision: str, nreq: int = SERVE_REQUESTS, n_scale: float = SERVE_N_SCALE,
+                   lam_fixed=SERVE_LAMBDA):
     import paper_2509_07974_amd as fp
     from paper_2509_07974_amd.serve import Job, Server, latency_stats
     import synth
     t = time.perf_counter()
-    reqs = synth.serving_requests(SERVE_REQUESTS, n_scale=SERVE_N_SCALE)
-    cats = [synth.make_request_catalogue(r) for r in reqs]
+    reqs = synth.serving_requests(nreq, n_scale=n_scale)
+    cats = []
+    for k, r in enumerate(reqs):
+        cats.append(synth.make_request_catalogue(r))
+        if (k + 1) % 32 == 0:
+            log(f"serving: generated {k + 1} request catalogues")
     log(f"serving: generated {len(reqs)} request catalogues in {time.perf_counter() - t:.1f} s")
 
     def jobs():
@@ -136,14 +143,16 @@ def serving_report(precision: str):
 
     alone = jobs()
     service = []
-    for j in alone:
+    for k, j in enumerate(alone):
         srv = Server()
         t = time.perf_counter()
         srv.submit(j)
         srv.drain()
         service.append(time.perf_counter() - t)
+        if (k + 1) % 16 == 0:
+            log(f"serving: alone pass {k + 1}/{len(alone)} requests, {sum(service):.1f} s")
     log(f"serving: alone pass {sum(service):.1f} s")
-    lam = SERVE_LAMBDA if SERVE_LAMBDA else 0.7 / float(np.mean(service))
+    lam = lam_fixed if lam_fixed else 0.7 / float(np.mean(service))
     rng = np.random.default_rng(SERVE_SEED)
     arrivals = np.cumsum(rng.exponential(1.0 / lam, len(reqs)))
     arrivals -= arrivals[0]
@@ -152,7 +161,20 @@ def serving_report(precision: str):
         j.arrival = float(a)
     srv = Server()
     t = time.perf_counter()
-    srv.run(mix)
+    # Server.run, with a progress line every 30 s
+    todo = sorted(mix, key=lambda j: j.arrival)
+    srv.t0 = srv.clock()
+    k, last = 0, time.perf_counter()
+    while k < len(todo) or not srv.idle():
+        now = srv.now()
+        while k < len(todo) and todo[k].arrival <= now:
+            srv.submit(todo[k])
+            k += 1
+        if not srv.poll():
+            time.sleep(2e-4)
+        if time.perf_counter() - last > 30.0:
+            last = time.perf_counter()
+            log(f"serving: mix pass {len(srv.finished)}/{len(mix)} finished")
     wall = time.perf_counter() - t
     stats = latency_stats(mix)
     equal = all(m.state == "done" and a.state == "done" and np.array_equal(m.result, a.result)
@@ -160,15 +182,33 @@ def serving_report(precision: str):
     centres = sum(j.n for j in mix if j.state == "done")
     log(f"serving: mix pass {wall:.1f} s, p50 {stats['p50_s']:.3f} s, p99 {stats['p99_s']:.3f} s")
     return {"requests": len(mix), "precision": precision, "lambda_per_s": lam,
-            "lambda_source": "fixed" if SERVE_LAMBDA else "0.7 / mean alone service time",
+            "lambda_source": "fixed" if lam_fixed else "0.7 / mean alone service time",
             "p50_latency_s": stats["p50_s"], "p99_latency_s": stats["p99_s"],
             "mean_latency_s": stats["mean_s"], "max_latency_s": stats["max_s"],
             "service_alone_p50_s": float(np.median(service)), "service_alone_mean_s": float(np.mean(service)),
             "wall_s": wall, "centres_per_s": centres / wall,
             "hbm_budget_bytes": srv.budget, "peak_admitted_bytes": srv.peak_used,
             "mix_equals_alone": bool(equal),
-            "stream": f"seeded requests 0..{len(mix) - 1} (seeds 1000+r), N scaled by {SERVE_N_SCALE}, "
+            "stream": f"seeded requests 0..{len(mix) - 1} (seeds 1000+r), N scaled by {n_scale}, "
                       f"Poisson arrivals seed {SERVE_SEED}"}
+
+
+def stage_b_roofline(ncent, nb, nmax, precision, ms):
+    """MFMA roofline of the contraction: useful flops (8 per complex
+    multiply-add, 9 nb^3 (2nmax+1)^2 per centre) and issued flops (rows of
+    each correlator group padded to 16, K split into real and imaginary
+    parts, x3 for the hi/lo products of the 16-bit paths), over the measured
+    stage time."""
+    nn = 2 * nmax + 1
+    useful = 8.0 * 9 * nb ** 3 * nn * nn * ncent
+    rows = [2 * 2 * nb] * 2 + [2 * nb] * 5           # groups {0,3}, {1,6} and five single ones
+    rows = [(r + 15) // 16 * 16 for r in rows]
+    issued = sum(rows) * nb * nb * 2 * 2 * nn * nn * ncent * (1 if precision == "fp64" else 3)
+    peak = PEAK_FP64_MFMA if precision == "fp64" else PEAK_F16_MFMA
+    t = ms * 1e-3
+    return {"bound": "mfma", "useful_tflops": useful / t / 1e12, "issued_tflops": issued / t / 1e12,
+            "peak": peak / 1e12, "unit": "TFLOP/s", "frac_issued": issued / t / peak,
+            "frac_useful": useful / t / peak, "stage_ms": ms}
 
 
 THREEPCF_NMAX = 10   # 3PCF multipoles |n| <= 10 (stage (a) records of order 5)
@@ -222,6 +262,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the mock request-stream latency report")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 mixed-path run")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the request-stream report (with --serve-requests / --serve-n-scale)")
+    ap.add_argument("--serve-requests", type=int, default=SERVE_REQUESTS)
+    ap.add_argument("--serve-n-scale", type=float, default=SERVE_N_SCALE)
+    ap.add_argument("--serve-lambda", type=float, default=SERVE_LAMBDA or 0.0,
+                    help="arrival rate (requests/s); 0 = 0.7 / mean alone service time")
     ap.add_argument("--no-3pcf", action="store_true", help="skip the 3PCF run on the same catalogue")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (counter calibration)")
@@ -233,6 +279,10 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.serving_only:
+        rep = serving_report(args.precision, args.serve_requests, args.serve_n_scale, args.serve_lambda or None)
+        print(json.dumps({"serving": rep}))
         return
 
     import torch
@@ -284,7 +334,9 @@ def main():
             "achieved_executed": executed / 1e12}
 
     extra = {"stage_ms_per_step": {k: prof[k + "_ms"] / steps for k in ("stage_a", "relayout", "stage_b", "corr")},
-             "generation_s": gen_s}
+             "generation_s": gen_s,
+             "roofline_stage_b": stage_b_roofline(cat.n, len(edges) - 1, nmax, args.precision,
+                                                  prof["stage_b_ms"] / steps)}
     log(f"timed {args.steps} steps: {dt:.3f} s/step")
     if not args.no_fp64 and args.precision != "fp64":
         ref = run("fp64")
@@ -328,7 +380,8 @@ def main():
                        "nbins": len(edges) - 1, "nmax": nmax, "precision": args.precision},
             "roofline": roof}
     if not args.no_serving:
-        extra["serving"] = serving_report(args.precision)
+        extra["serving"] = serving_report(args.precision, args.serve_requests, args.serve_n_scale,
+                                          args.serve_lambda or None)
         line["latency"] = {"p50_s": extra["serving"]["p50_latency_s"],
                            "p99_s": extra["serving"]["p99_latency_s"],
                            "workload": "mock request stream, see extra.serving"}

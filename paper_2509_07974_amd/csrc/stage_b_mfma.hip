@@ -114,6 +114,21 @@ struct Half8<FPCF4_MIXED_BF16> {
 
 typedef __fp16 h2 __attribute__((ext_vector_type(2)));
 
+// lo = fp16(v - hi) for a packed pair: v_fma_mix{lo,hi}_f16 form v*1 - hi
+// with hi read as fp16 from its half of the packed register (exact in
+// binary32, since hi is v truncated) and round the result to fp16 into the
+// low / high half of the destination.  The compiler does not select these
+// from plain code when binary32 denormals are enabled; only the fp16 result
+// of a tiny lo could differ, and lo only refines hi.
+__device__ __forceinline__ h2 split_lo2(float x0, float x1, h2 hh) {
+  h2 lo;
+  asm("v_fma_mixlo_f16 %0, %1, 1.0, -%3 op_sel_hi:[0,0,1]\n\t"
+      "v_fma_mixhi_f16 %0, %2, 1.0, -%3 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+      : "=&v"(lo)
+      : "v"(x0), "v"(x1), "v"(hh));
+  return lo;
+}
+
 template <int PREC>
 __device__ __forceinline__ void split8v(const float (&v)[8], typename Half8<PREC>::type& hi,
                                         typename Half8<PREC>::type& lo) {
@@ -122,9 +137,7 @@ __device__ __forceinline__ void split8v(const float (&v)[8], typename Half8<PREC
 #pragma unroll
     for (int q = 0; q < 8; q += 2) {
       const h2 hh = __builtin_amdgcn_cvt_pkrtz(v[q], v[q + 1]);
-      // v - hi is exact in binary32 (one mixed-precision fma each)
-      const h2 ll = __builtin_amdgcn_cvt_pkrtz(__builtin_fmaf(-(float)hh[0], 1.0f, v[q]),
-                                               __builtin_fmaf(-(float)hh[1], 1.0f, v[q + 1]));
+      const h2 ll = split_lo2(v[q], v[q + 1], hh);
       hi[q] = (_Float16)hh[0];
       hi[q + 1] = (_Float16)hh[1];
       lo[q] = (_Float16)ll[0];
