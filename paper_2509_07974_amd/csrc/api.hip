@@ -66,8 +66,9 @@ struct PlanInfo {
   size_t sort_tmp = 0;
   // persistent buffers
   size_t o_gal, o_cells, o_centres, o_e2, o_edges, o_counters, o_bbox, o_bad,
-      o_pairs, o_part, o_ups, o_corr, o_cpart, o_acc3, o_part3, o_xg, o_xw, o_counts, o_aos,
-      o_region;
+      o_pairs, o_part, o_ups, o_bpart, o_corr, o_cpart, o_acc3, o_part3, o_xg, o_xw, o_counts,
+      o_aos, o_region;
+  int bslices = 1;             // centre slices of the contraction (partials when > 1)
   size_t region = 0;           // records of one tile, or create-time temporaries
   // create-time temporaries inside the region
   size_t t_raw, t_key_a, t_key_b, t_idx_a, t_idx_b, t_inv, t_sort, t_cent64;
@@ -147,6 +148,8 @@ fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   P.corr_bytes = order == 4 ? corr_elems(P.nb, P.nmax) * 16 : 0;
   P.acc3_bytes = order == 3 ? three_elems(P.nb, m3) * 16 : 0;
   P.o_ups = take(P.ups_bytes);
+  P.bslices = order == 4 ? contract_slices((int)std::min<int64_t>(P.tile, INT32_MAX), P.nmax) : 1;
+  P.o_bpart = take(P.bslices > 1 ? P.ups_bytes * P.bslices : 0);
   P.o_corr = take(P.corr_bytes);
   P.o_cpart = take(P.corr_bytes * CORR_SLICES);
   P.o_acc3 = take(P.acc3_bytes);
@@ -383,6 +386,7 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
     b.nmax = P.nmax;
     b.ups = R->at<double>(P.o_ups);
     b.corr = R->at<double>(P.o_corr);
+    b.part = P.bslices > 1 ? R->at<double>(P.o_bpart) : nullptr;
     HIPCHK(launch_contract(b, P.precision, (int)P.ldc, a.xg, a.xw, a.maxima, s));
     if (prof) HIPCHK(hipEventRecord(evs[3], s));
     CorrArgs ca{a.rec, a.xg, a.xw, ncent, P.nb, P.nmax, (int32_t)P.ldc, b.corr,

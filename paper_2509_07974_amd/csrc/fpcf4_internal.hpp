@@ -124,7 +124,23 @@ struct StageBArgs {
   int32_t nmax;
   double* ups;              // [9][nb][nb][nb][nn][nn] complex128 accumulator
   double* corr;             // correction sums (see stage_b.hip)
+  double* part;             // [contract_slices][9 nb^3 nn^2] complex partials, or null (one slice)
 };
+
+// Centre slices of the contraction: enough workgroups (one per (n2, n3) and
+// slice) to fill the chip, at least 2048 centres per slice, at most 8.
+__host__ __device__ inline int contract_slices(int ncent, int nmax) {
+  const int nn2 = (2 * nmax + 1) * (2 * nmax + 1);
+  int s = (2048 + nn2 - 1) / nn2;
+  s = imin(s, 8);
+  s = imin(s, imax(1, ncent / 2048));
+  return imax(s, 1);
+}
+// centres per slice (a multiple of the 32-centre staging chunk)
+__host__ __device__ inline int contract_slice_len(int ncent, int nsl) {
+  const int per = (ncent + nsl - 1) / nsl;
+  return (per + 31) / 32 * 32;
+}
 
 struct CorrArgs {
   const void* rec;

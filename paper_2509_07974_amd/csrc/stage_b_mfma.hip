@@ -209,8 +209,11 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
   const int mrows = GR.nmu * 2 * nb;
   const int ncols = nb * nb;
   const int ntiles = (ncols + 15) >> 4;
-  const int ncent = a.s.ncent;
-  const float* rec = reinterpret_cast<const float*>(a.s.rec);
+  // centre slice of this workgroup (blockIdx.y): centres [cbase, cbase + ncent)
+  const int per = contract_slice_len(a.s.ncent, (int)gridDim.y);
+  const int cbase = (int)blockIdx.y * per;
+  const int ncent = imax(0, imin(a.s.ncent - cbase, per));
+  const float* rec = reinterpret_cast<const float*>(a.s.rec) + 2 * (int64_t)cbase;
   const int ldc = a.ldc;
 
   const int rowA = fac_entry_k(L, F0.A, F0.A.a * n2 + F0.A.b * n3 + F0.A.c);
@@ -244,8 +247,8 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
   }
 
   // ---- staging: global -> registers (issue), registers -> LDS (commit)
-  const C2<float>* xg = reinterpret_cast<const C2<float>*>(a.xg);
-  const float* xw = reinterpret_cast<const float*>(a.xw);
+  const C2<float>* xg = reinterpret_cast<const C2<float>*>(a.xg) + cbase;
+  const float* xw = reinterpret_cast<const float*>(a.xw) + cbase;
   Prefetch<float, NXS, NYS> pf;
   // this thread's Y slots (K-step, row tile, lane) and their row meaning
   int y_ks[NYS], y_m[NYS], y_l[NYS], y_part[NYS], y_b2[NYS], y_row[NYS], y_cj[NYS];
@@ -361,8 +364,10 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
 
   const int nchunks = (ncent + KC - 1) / KC;
   __syncthreads();              // scales visible
-  issue(0);
-  commit(0, 0);
+  if (ncent > 0) {              // uniform: an empty slice only writes zeros
+    issue(0);
+    commit(0, 0);
+  }
   __syncthreads();
   for (int ch = 0; ch < nchunks; ++ch) {
     const int buf = ch & 1;
@@ -416,7 +421,9 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
     __syncthreads();
   }
 
-  // write: D row = 4*(lane/16) + r in tile m, column = lane%16 in tile t
+  // write: D row = 4*(lane/16) + r in tile m, column = lane%16 in tile t.  With
+  // several centre slices each slice writes its own binary64 partial buffer.
+  const int64_t ups2 = 2 * (int64_t)9 * nb * nb * nb * nn * nn;
 #pragma unroll
   for (int t = 0; t < NTW; ++t) {
     if (!colok[t]) continue;
@@ -431,7 +438,9 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
         const int mu = mi ? GR.mu[1] : GR.mu[0];
         const double unscale = 1.0 / ((double)sc_lds[0][b1] * sc_lds[1][b2] * sc_lds[2][b3]);
         const int64_t o = (((((int64_t)mu * nb + b1) * nb + b2) * nb + b3) * nn + (n2 + n)) * nn + (n3 + n);
-        a.s.ups[2 * o + part] += acc64[m][t][r] * unscale;
+        const double v = acc64[m][t][r] * unscale;
+        if (gridDim.y == 1) a.s.ups[2 * o + part] += v;
+        else a.s.part[(int64_t)blockIdx.y * ups2 + 2 * o + part] = v;
       }
     }
   }
@@ -464,8 +473,10 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
   const int mrows = GR.nmu * 2 * nb;
   const int ncols = nb * nb;
   const int ntiles = (ncols + 15) >> 4;
-  const int ncent = a.s.ncent;
-  const double* rec = reinterpret_cast<const double*>(a.s.rec);
+  const int per = contract_slice_len(a.s.ncent, (int)gridDim.y);
+  const int cbase = (int)blockIdx.y * per;
+  const int ncent = imax(0, imin(a.s.ncent - cbase, per));
+  const double* rec = reinterpret_cast<const double*>(a.s.rec) + 2 * (int64_t)cbase;
   const int ldc = a.ldc;
   const int rowA = fac_entry_k(L, F0.A, F0.A.a * n2 + F0.A.b * n3 + F0.A.c);
   const int rowC = fac_entry_k(L, F0.C, F0.C.b * n3 + F0.C.c);
@@ -476,8 +487,8 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
   __shared__ C2<double> Zs[2][16][KC + 1];
   __shared__ C2<double> Ys[2][GR.nmu][16][KC + 1];   // [mu idx][b2][centre]
 
-  const C2<double>* xg = reinterpret_cast<const C2<double>*>(a.xg);
-  const double* xw = reinterpret_cast<const double*>(a.xw);
+  const C2<double>* xg = reinterpret_cast<const C2<double>*>(a.xg) + cbase;
+  const double* xw = reinterpret_cast<const double*>(a.xw) + cbase;
   struct PF {
     C2<double> xc, av, cv, y0, y1;
   } pf[NXS];
@@ -546,8 +557,10 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
 
   const int nchunks = (ncent + KC - 1) / KC;
   const int kq = lane >> 4;  // k within the K=4 step: (centre = kq/2, part = kq%2)
-  issue(0);
-  commit(0, 0);
+  if (ncent > 0) {           // uniform: an empty slice only writes zeros
+    issue(0);
+    commit(0, 0);
+  }
   __syncthreads();
   for (int ch = 0; ch < nchunks; ++ch) {
     const int buf = ch & 1;
@@ -581,7 +594,9 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
     __syncthreads();
   }
 
-  // f64 D layout: element r of lane L is row 4 r + L/16, column L%16
+  // f64 D layout: element r of lane L is row 4 r + L/16, column L%16.  With
+  // several centre slices each slice writes its own partial buffer.
+  const int64_t ups2 = 2 * (int64_t)9 * nb * nb * nb * nn * nn;
 #pragma unroll
   for (int t = 0; t < NTW; ++t) {
     if (!colok[t]) continue;
@@ -595,16 +610,17 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
         const int mi = row / (2 * nb), rem = row % (2 * nb), part = rem / nb, b2 = rem % nb;
         const int mu = mi ? GR.mu[1] : GR.mu[0];
         const int64_t o = (((((int64_t)mu * nb + b1) * nb + b2) * nb + b3) * nn + (n2 + n)) * nn + (n3 + n);
-        a.s.ups[2 * o + part] += acc[m][t][r];
+        if (gridDim.y == 1) a.s.ups[2 * o + part] += acc[m][t][r];
+        else a.s.part[(int64_t)blockIdx.y * ups2 + 2 * o + part] = acc[m][t][r];
       }
     }
   }
 }
 
 template <int G, int NBC>
-static void launch_group_nbc(const BArgs& a, int precision, hipStream_t s) {
+static void launch_group_nbc(const BArgs& a, int precision, int nsl, hipStream_t s) {
   const int nn = 2 * a.s.nmax + 1;
-  const dim3 grid(nn * nn), block(64 * wb_of(NBC));
+  const dim3 grid(nn * nn, nsl), block(64 * wb_of(NBC));
   if (precision == FPCF4_FP64)
     hipLaunchKernelGGL((contract_f64_kernel<G, NBC>), grid, block, 0, s, a);
   else if (precision == FPCF4_MIXED_FP16)
@@ -614,25 +630,43 @@ static void launch_group_nbc(const BArgs& a, int precision, hipStream_t s) {
 }
 
 template <int G>
-static hipError_t launch_group(const BArgs& a, int precision, hipStream_t s) {
-  if (a.s.nb <= 8) launch_group_nbc<G, 8>(a, precision, s);
-  else if (a.s.nb <= 12) launch_group_nbc<G, 12>(a, precision, s);
-  else launch_group_nbc<G, 16>(a, precision, s);
+static hipError_t launch_group(const BArgs& a, int precision, int nsl, hipStream_t s) {
+  if (a.s.nb <= 8) launch_group_nbc<G, 8>(a, precision, nsl, s);
+  else if (a.s.nb <= 12) launch_group_nbc<G, 12>(a, precision, nsl, s);
+  else launch_group_nbc<G, 16>(a, precision, nsl, s);
   return hipGetLastError();
+}
+
+// ups[i] += sum of the slice partials, slices in order
+__global__ void contract_reduce_kernel(const double* part, int nsl, int64_t n2, double* ups) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n2) return;
+  double v = 0.0;
+  for (int k = 0; k < nsl; ++k) v += part[(int64_t)k * n2 + i];
+  ups[i] += v;
 }
 
 hipError_t launch_contract(const StageBArgs& sb, int precision, int ldc, const void* xg,
                            const void* xw, const unsigned* maxima, hipStream_t s) {
   if (sb.ncent <= 0) return hipSuccess;
   BArgs a{sb, ldc, xg, xw, maxima};
+  const int nsl = sb.part ? contract_slices(sb.ncent, sb.nmax) : 1;
   hipError_t e;
-  if ((e = launch_group<0>(a, precision, s)) != hipSuccess) return e;
-  if ((e = launch_group<1>(a, precision, s)) != hipSuccess) return e;
-  if ((e = launch_group<2>(a, precision, s)) != hipSuccess) return e;
-  if ((e = launch_group<3>(a, precision, s)) != hipSuccess) return e;
-  if ((e = launch_group<4>(a, precision, s)) != hipSuccess) return e;
-  if ((e = launch_group<5>(a, precision, s)) != hipSuccess) return e;
-  return launch_group<6>(a, precision, s);
+  if ((e = launch_group<0>(a, precision, nsl, s)) != hipSuccess) return e;
+  if ((e = launch_group<1>(a, precision, nsl, s)) != hipSuccess) return e;
+  if ((e = launch_group<2>(a, precision, nsl, s)) != hipSuccess) return e;
+  if ((e = launch_group<3>(a, precision, nsl, s)) != hipSuccess) return e;
+  if ((e = launch_group<4>(a, precision, nsl, s)) != hipSuccess) return e;
+  if ((e = launch_group<5>(a, precision, nsl, s)) != hipSuccess) return e;
+  if ((e = launch_group<6>(a, precision, nsl, s)) != hipSuccess) return e;
+  if (nsl > 1) {
+    const int nn = 2 * sb.nmax + 1;
+    const int64_t n2 = 2 * (int64_t)9 * sb.nb * sb.nb * sb.nb * nn * nn;
+    hipLaunchKernelGGL(contract_reduce_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s,
+                       (const double*)sb.part, nsl, n2, sb.ups);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 }  // namespace fpcf4
