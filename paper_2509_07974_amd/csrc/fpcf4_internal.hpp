@@ -131,9 +131,9 @@ struct StageBArgs {
 // slice) to fill the chip, at least 2048 centres per slice, at most 8.
 __host__ __device__ inline int contract_slices(int ncent, int nmax) {
   const int nn2 = (2 * nmax + 1) * (2 * nmax + 1);
-  int s = (2048 + nn2 - 1) / nn2;
-  s = imin(s, 8);
-  s = imin(s, imax(1, ncent / 2048));
+  int s = (8192 + nn2 - 1) / nn2;
+  s = imin(s, 32);
+  s = imin(s, imax(1, ncent / 8192));
   return imax(s, 1);
 }
 // centres per slice (a multiple of the 32-centre staging chunk)
