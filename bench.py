@@ -211,6 +211,29 @@ def stage_b_roofline(ncent, nb, nmax, precision, ms):
             "frac_useful": useful / t / peak, "stage_ms": ms}
 
 
+NATURAL_NPHI = 129   # angular bins per axis of the natural components (the paper's choice)
+
+
+def natural_report(fp, ups_dev, nphi, block=256):
+    """Natural components of every radial-bin triplet of the result, streamed
+    in blocks on the device (nothing of size nbins^3 nphi^2 is kept)."""
+    import torch
+    nb = ups_dev.shape[1]
+    for _ in fp.natural_blocks(ups_dev, nphi, block=block):   # warm-up pass
+        break
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    n = 0
+    for trip, gam, nrm in fp.natural_blocks(ups_dev, nphi, block=block):
+        n += len(trip)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    log(f"natural components: {n} triplets x {nphi}^2 angles in {dt:.3f} s")
+    return {"nphi": nphi, "triplets": n, "block": block, "seconds": dt,
+            "values_per_s": 9 * n * nphi * nphi / dt,
+            "streamed_bytes": 8 * n * nphi * nphi * 16 + n * nphi * nphi * 8}
+
+
 THREEPCF_NMAX = 10   # 3PCF multipoles |n| <= 10 (stage (a) records of order 5)
 
 
@@ -269,6 +292,8 @@ def main():
     ap.add_argument("--serve-lambda", type=float, default=SERVE_LAMBDA or 0.0,
                     help="arrival rate (requests/s); 0 = 0.7 / mean alone service time")
     ap.add_argument("--no-3pcf", action="store_true", help="skip the 3PCF run on the same catalogue")
+    ap.add_argument("--no-natural", action="store_true",
+                    help="skip the blockwise natural-component conversion of the result")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -369,6 +394,8 @@ def main():
                               [float(np.linalg.norm(c[m] - b[m]) / np.linalg.norm(b[m])) for m in range(9)]})
             log(f"bf16: {dtb:.3f} s/step")
         del ref
+    if not args.no_natural:
+        extra["natural_blocks"] = natural_report(fp, out, NATURAL_NPHI)
     if not args.no_3pcf:
         extra["threepcf"] = threepcf_report(fp, dev, cat.n, edges, args.precision, args.no_fp64)
     line = {"metric": METRIC, "value": value, "unit": "centres/s", "n_gpus": 1,

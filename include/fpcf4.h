@@ -175,6 +175,24 @@ fpcf4_status fpcf4_to_natural(const double *upsilon, int32_t nbins,
                               int32_t nmax, int32_t nphi, double *gamma_out,
                               double *norm_out, void *stream);
 
+/* The same conversion for a caller-chosen list of radial-bin triplets only,
+ * so that a large multipole tensor can be turned into natural components
+ * block by block without materialising nbins^3 * nphi^2 values (device
+ * memory used: about 9 * ntrip * ((2nmax+1)^2 + nphi (2nmax+1) + nphi^2)
+ * complex128 plus the input when it is on the host).
+ * upsilon: [9][nbins][nbins][nbins][2nmax+1][2nmax+1] complex128 as returned
+ *   by estimate_4pcf_multipoles, in host or device memory (ups_mem).
+ * triplets: host int32 [ntrip][3] = (b1, b2, b3), each in [0, nbins).
+ * gamma_out: complex128 [8][ntrip][nphi][nphi]; norm_out (may be NULL):
+ *   float64 [ntrip][nphi][nphi]; both in host or device memory (out_mem).
+ * Same angular binning, normalisation and zero rule as fpcf4_to_natural;
+ * synchronous with respect to `stream` on return.  0 <= ntrip <= 2^24. */
+fpcf4_status fpcf4_to_natural_triplets(const double *upsilon, int32_t ups_mem,
+                                       int32_t nbins, int32_t nmax, int32_t nphi,
+                                       const int32_t *triplets, int64_t ntrip,
+                                       double *gamma_out, double *norm_out,
+                                       int32_t out_mem, void *stream);
+
 /* ------------------------------------------------------------------------
  * Request API for serving: the caller sizes and owns the device workspace
  * (admission by HBM footprint), then advances the request one centre tile

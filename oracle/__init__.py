@@ -7,6 +7,7 @@ from .estimator import (NCORR, FACTORS, TABLE1, family_orders, squared_edges,
                         centre_neighbours, bin_counts, centre_multipoles,
                         multipoles, contract, upsilon, upsilon_parallel)
 from .brute import brute_upsilon, brute_angular_bins
-from .natural import angular_integrals, binned_from_multipoles, natural_components
+from .natural import (angular_integrals, binned_from_multipoles, natural_components,
+                      natural_components_triplets)
 from .nthorder import (beta_matrix, arg_coefficients, norm_coefficients, upsilon_n, upsilon3,
                        brute_upsilon3)

@@ -41,7 +41,18 @@ def binned_from_multipoles(ups: np.ndarray, nphi: int) -> np.ndarray:
 def natural_components(ups: np.ndarray, nphi: int):
     """(Gamma[8, nb, nb, nb, nphi, nphi] complex, Nbar[nb, nb, nb, nphi, nphi]
     real).  Gamma is Ubar_mu / Nbar where Nbar != 0, else 0."""
-    binned = binned_from_multipoles(ups, nphi)
+    return _ratio(binned_from_multipoles(ups, nphi))
+
+
+def natural_components_triplets(ups: np.ndarray, nphi: int, triplets):
+    """The conversion above for the listed radial-bin triplets (b1, b2, b3)
+    only: (Gamma[8, ntrip, nphi, nphi], Nbar[ntrip, nphi, nphi])."""
+    t = np.asarray(triplets, dtype=np.int64).reshape(-1, 3)
+    sel = ups[:, t[:, 0], t[:, 1], t[:, 2]]               # [9, ntrip, nn, nn]
+    return _ratio(binned_from_multipoles(sel[:, :, None, None], nphi)[:, :, 0, 0])
+
+
+def _ratio(binned):
     nbar = binned[8].real
     with np.errstate(divide="ignore", invalid="ignore"):
         gam = np.where(nbar != 0.0, binned[:8] / np.where(nbar != 0.0, nbar, 1.0), 0.0)

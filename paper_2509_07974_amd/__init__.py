@@ -16,7 +16,8 @@ from . import _lib
 from ._lib import (FP64, MIXED_FP16, MIXED_BF16, MEM_HOST, MEM_DEVICE, NMAX_SUPPORTED,
                    NBINS_SUPPORTED, Fpcf4Error, check, lib)
 
-__all__ = ["estimate_4pcf_multipoles", "estimate_3pcf_multipoles", "debug_multipoles", "to_natural", "plan", "Request",
+__all__ = ["estimate_4pcf_multipoles", "estimate_3pcf_multipoles", "debug_multipoles", "to_natural",
+           "to_natural_triplets", "natural_blocks", "plan", "Request",
            "profile_enable", "profile_read",
            "PRECISIONS", "Fpcf4Error", "output_shape", "output3_shape", "lib", "version"]
 
@@ -163,6 +164,47 @@ def to_natural(upsilon, nphi: int, stream=None):
     check(lib().fpcf4_to_natural(C.c_void_p(u.ctypes.data), nb, nmax, int(nphi),
                                  C.c_void_p(gam.ctypes.data), C.c_void_p(nrm.ctypes.data), stream))
     return gam, nrm
+
+
+def to_natural_triplets(upsilon, nphi: int, triplets, stream=None):
+    """Natural components for the listed radial-bin triplets only:
+    (Gamma complex128 [8, ntrip, nphi, nphi], Nbar float64 [ntrip, nphi, nphi]).
+    upsilon is the multipole tensor (NumPy, or a torch tensor on the GPU, in
+    which case the results are torch tensors on the same device)."""
+    t = np.ascontiguousarray(np.asarray(triplets, dtype=np.int32).reshape(-1, 3))
+    ntrip = t.shape[0]
+    if _is_torch_device(upsilon):
+        import torch
+        u = upsilon.contiguous()
+        nb, nmax = u.shape[1], (u.shape[-1] - 1) // 2
+        gam = torch.empty((8, ntrip, nphi, nphi), dtype=torch.complex128, device=u.device)
+        nrm = torch.empty((ntrip, nphi, nphi), dtype=torch.float64, device=u.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(u.device).cuda_stream
+        check(lib().fpcf4_to_natural_triplets(C.c_void_p(u.data_ptr()), MEM_DEVICE, nb, nmax, int(nphi),
+                                              C.c_void_p(t.ctypes.data), ntrip, C.c_void_p(gam.data_ptr()),
+                                              C.c_void_p(nrm.data_ptr()), MEM_DEVICE, stream))
+        return gam, nrm
+    u = np.ascontiguousarray(np.asarray(upsilon, dtype=np.complex128))
+    nb, nmax = u.shape[1], (u.shape[-1] - 1) // 2
+    gam = np.empty((8, ntrip, nphi, nphi), dtype=np.complex128)
+    nrm = np.empty((ntrip, nphi, nphi), dtype=np.float64)
+    check(lib().fpcf4_to_natural_triplets(C.c_void_p(u.ctypes.data), MEM_HOST, nb, nmax, int(nphi),
+                                          C.c_void_p(t.ctypes.data), ntrip, C.c_void_p(gam.ctypes.data),
+                                          C.c_void_p(nrm.ctypes.data), MEM_HOST, stream))
+    return gam, nrm
+
+
+def natural_blocks(upsilon, nphi: int, block: int = 4096, stream=None):
+    """Yield (triplets [k, 3], Gamma [8, k, nphi, nphi], Nbar [k, nphi, nphi])
+    over all radial-bin triplets in blocks of at most `block`, so that the
+    natural components of a large tensor can be consumed on the fly."""
+    nb = upsilon.shape[1]
+    allt = np.stack(np.meshgrid(np.arange(nb), np.arange(nb), np.arange(nb), indexing="ij"), -1).reshape(-1, 3)
+    for s in range(0, allt.shape[0], block):
+        t = allt[s:s + block]
+        gam, nrm = to_natural_triplets(upsilon, nphi, t, stream)
+        yield t, gam, nrm
 
 
 def profile_enable(on: bool = True):

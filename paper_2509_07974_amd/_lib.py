@@ -100,6 +100,10 @@ def lib():
     L.estimate_3pcf_multipoles.restype = C.c_int32
     L.fpcf4_output3_elems.argtypes = [C.c_int32, C.c_int32]
     L.fpcf4_output3_elems.restype = C.c_int64
+    L.fpcf4_to_natural_triplets.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                            C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32,
+                                            C.c_void_p]
+    L.fpcf4_to_natural_triplets.restype = C.c_int32
     _lib = L
     return L
 
@@ -114,4 +118,5 @@ EXPORTED = [
     "fpcf4_request_create", "fpcf4_request_step", "fpcf4_request_finalize",
     "fpcf4_request_destroy", "fpcf4_last_error", "fpcf4_version", "fpcf4_output_elems",
     "fpcf4_profile_enable", "fpcf4_profile_read", "estimate_3pcf_multipoles", "fpcf4_output3_elems",
+    "fpcf4_to_natural_triplets",
 ]

@@ -20,6 +20,9 @@ hipError_t cells_build(const double*, const double*, const double*, const double
 hipError_t cells_centre_order(const uint32_t*, int64_t, const Grid&, uint32_t*, uint32_t*, int32_t*,
                               int32_t*, void*, size_t, hipStream_t);
 hipError_t cells_map_centres(const int64_t*, int64_t, const int32_t*, int32_t*, hipStream_t);
+hipError_t natural_triplets(const double* ups, int nb, int nmax, int nphi, const int32_t* trip,
+                            int64_t ntrip, double* sel, double* tmp, double* binned, double* gamma,
+                            double* norm, hipStream_t s);
 hipError_t natural_components(const double* ups_dev, int nb, int nmax, int nphi, double* tmp,
                               double* gamma_dev, double* norm_dev, hipStream_t s);
 }  // namespace fpcf4
@@ -671,6 +674,59 @@ fpcf4_status fpcf4_to_natural(const double* upsilon, int32_t nbins, int32_t nmax
   if (e == hipSuccess && norm_out) e = hipMemcpyAsync(norm_out, dn, n_b, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) st = fail(FPCF4_E_DEVICE, "to_natural: %s", hipGetErrorString(e));
+  (void)hipFreeAsync(buf, s);
+  (void)hipStreamSynchronize(s);
+  return st;
+}
+
+fpcf4_status fpcf4_to_natural_triplets(const double* upsilon, int32_t ups_mem, int32_t nbins,
+                                       int32_t nmax, int32_t nphi, const int32_t* triplets,
+                                       int64_t ntrip, double* gamma_out, double* norm_out,
+                                       int32_t out_mem, void* stream) {
+  if (!upsilon || !gamma_out || (ntrip > 0 && !triplets)) return fail(FPCF4_E_INVALID_ARG, "null argument");
+  if (ups_mem != FPCF4_MEM_HOST && ups_mem != FPCF4_MEM_DEVICE) return fail(FPCF4_E_INVALID_ARG, "ups_mem %d", ups_mem);
+  if (out_mem != FPCF4_MEM_HOST && out_mem != FPCF4_MEM_DEVICE) return fail(FPCF4_E_INVALID_ARG, "out_mem %d", out_mem);
+  if (nbins < 1 || nbins > FPCF4_NBINS_SUPPORTED) return fail(FPCF4_E_INVALID_ARG, "nbins %d", nbins);
+  if (nmax < 0 || nmax > FPCF4_NMAX_SUPPORTED) return fail(FPCF4_E_INVALID_ARG, "nmax %d", nmax);
+  if (nphi < 1 || nphi > 4096) return fail(FPCF4_E_INVALID_ARG, "nphi %d", nphi);
+  if (ntrip < 0 || ntrip > (int64_t(1) << 24)) return fail(FPCF4_E_INVALID_ARG, "ntrip %lld", (long long)ntrip);
+  for (int64_t t = 0; t < 3 * ntrip; ++t)
+    if (triplets[t] < 0 || triplets[t] >= nbins)
+      return fail(FPCF4_E_INVALID_ARG, "triplet bin %d out of range", triplets[t]);
+  if (ntrip == 0) return FPCF4_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  setup_pool();
+  const int64_t nn = 2 * nmax + 1;
+  const size_t in_b = ups_mem == FPCF4_MEM_HOST ? (size_t)fpcf4_output_elems(nbins, nmax) * 16 : 0;
+  const size_t trip_b = (size_t)ntrip * 3 * 4;
+  const size_t sel_b = (size_t)(9 * ntrip * nn * nn) * 16;
+  const size_t tmp_b = (size_t)(9 * ntrip * nphi * nn) * 16;
+  const size_t bin_b = (size_t)(9 * ntrip * nphi * nphi) * 16;
+  const size_t g_b = out_mem == FPCF4_MEM_HOST ? (size_t)(8 * ntrip * nphi * nphi) * 16 : 0;
+  const size_t n_b = (size_t)(ntrip * nphi * nphi) * 8;   // always staged unless written in place
+  const size_t o_in = 0, o_trip = up(in_b), o_sel = o_trip + up(trip_b), o_tmp = o_sel + up(sel_b),
+               o_bin = o_tmp + up(tmp_b), o_g = o_bin + up(bin_b), o_n = o_g + up(g_b),
+               total = o_n + up(n_b);
+  char* buf = nullptr;
+  HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&buf), total, s));
+  const double* ups = ups_mem == FPCF4_MEM_HOST ? reinterpret_cast<const double*>(buf + o_in) : upsilon;
+  const bool dev_out = out_mem == FPCF4_MEM_DEVICE;
+  double* gdst = dev_out ? gamma_out : reinterpret_cast<double*>(buf + o_g);
+  double* ndst = dev_out && norm_out ? norm_out : reinterpret_cast<double*>(buf + o_n);
+  fpcf4_status st = FPCF4_OK;
+  hipError_t e = hipSuccess;
+  if (in_b) e = hipMemcpyAsync(buf + o_in, upsilon, in_b, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(buf + o_trip, triplets, trip_b, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = natural_triplets(ups, nbins, nmax, nphi, reinterpret_cast<const int32_t*>(buf + o_trip), ntrip,
+                         reinterpret_cast<double*>(buf + o_sel), reinterpret_cast<double*>(buf + o_tmp),
+                         reinterpret_cast<double*>(buf + o_bin), gdst, ndst, s);
+  if (e == hipSuccess && !dev_out) {
+    e = hipMemcpyAsync(gamma_out, gdst, g_b, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && norm_out) e = hipMemcpyAsync(norm_out, ndst, n_b, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) st = fail(FPCF4_E_DEVICE, "to_natural_triplets: %s", hipGetErrorString(e));
   (void)hipFreeAsync(buf, s);
   (void)hipStreamSynchronize(s);
   return st;

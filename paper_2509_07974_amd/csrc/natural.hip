@@ -83,6 +83,35 @@ __global__ void nat_divide(double* binned, int64_t per_mu, double* gamma, double
   }
 }
 
+// sel[mu][t][n2][n3] = ups[mu][b1][b2][b3][n2][n3] for the listed triplets
+__global__ void nat_gather(const double* ups, int nb, int nmax, const int32_t* trip, int64_t ntrip,
+                           double* sel) {
+  const int nn = 2 * nmax + 1;
+  const int64_t nn2 = (int64_t)nn * nn;
+  const int64_t total = 9 * ntrip * nn2;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i % nn2;
+    const int64_t t = (i / nn2) % ntrip;
+    const int64_t mu = i / (nn2 * ntrip);
+    const int64_t q = ((mu * nb + trip[3 * t]) * nb + trip[3 * t + 1]) * nb + trip[3 * t + 2];
+    sel[2 * i] = ups[2 * (q * nn2 + e)];
+    sel[2 * i + 1] = ups[2 * (q * nn2 + e) + 1];
+  }
+}
+
+hipError_t natural_triplets(const double* ups, int nb, int nmax, int nphi, const int32_t* trip,
+                            int64_t ntrip, double* sel, double* tmp, double* binned, double* gamma,
+                            double* norm, hipStream_t s) {
+  const int64_t nq = 9 * ntrip;
+  const int64_t per_mu = ntrip * nphi * nphi;
+  hipLaunchKernelGGL(nat_gather, dim3(2048), dim3(256), 0, s, ups, nb, nmax, trip, ntrip, sel);
+  hipLaunchKernelGGL(nat_pass1, dim3(2048), dim3(256), 0, s, sel, nq, nmax, nphi, tmp);
+  hipLaunchKernelGGL(nat_pass2, dim3(2048), dim3(256), 0, s, tmp, nq, nmax, nphi, binned);
+  hipLaunchKernelGGL(nat_divide, dim3(1024), dim3(256), 0, s, binned, per_mu, gamma, norm);
+  return hipGetLastError();
+}
+
 hipError_t natural_components(const double* ups, int nb, int nmax, int nphi, double* tmp,
                               double* gamma, double* norm, hipStream_t s) {
   const int64_t nq = 9LL * nb * nb * nb;

@@ -109,3 +109,22 @@ def test_3pcf_output_elems_and_null_output():
     assert lib.fpcf4_output3_elems(12, 10) == 5 * 144 * 21
     assert lib.fpcf4_output3_elems(-1, 2) == 0
     assert lib.estimate_3pcf_multipoles(None, None, None, None, 0) == _lib.E_INVALID_ARG
+
+
+@pytest.mark.parametrize("nphi,trip,code", [
+    (8, [[0, 0, 3]], -1),      # bin index out of range
+    (8, [[-1, 0, 0]], -1),
+    (0, [[0, 0, 0]], -1),      # no angular bin
+])
+def test_natural_triplets_invalid_arguments(nphi, trip, code):
+    from paper_2509_07974_amd import _lib
+    lib = ensure_built()
+    nb, nmax = 3, 1
+    ups = np.zeros(9 * nb ** 3 * 9, complex)
+    t = np.asarray(trip, dtype=np.int32)
+    gam = np.zeros(8 * len(trip) * max(nphi, 1) ** 2, complex)
+    st = lib.fpcf4_to_natural_triplets(C.c_void_p(ups.ctypes.data), _lib.MEM_HOST, nb, nmax, nphi,
+                                       C.c_void_p(t.ctypes.data), len(trip), C.c_void_p(gam.ctypes.data),
+                                       None, _lib.MEM_HOST, None)
+    assert st == code
+    assert lib.fpcf4_to_natural_triplets(None, 0, nb, nmax, 8, None, 0, None, None, 0, None) == -1

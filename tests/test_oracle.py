@@ -364,3 +364,19 @@ def test_natural_components_converge_to_brute_angular_bins():
         b = oracle.binned_from_multipoles(u, nphi)
         errs.append(np.linalg.norm(b[8] - ref[8]) / np.linalg.norm(ref[8]))
     assert errs[2] < errs[0]
+
+
+def test_natural_triplets_equal_slices_of_full_conversion():
+    """The per-triplet form of the FP64 tail (used to stream large tensors)
+    is the full conversion restricted to the listed triplets."""
+    rng = np.random.default_rng(17)
+    nb, nmax, nphi = 3, 2, 8
+    nn = 2 * nmax + 1
+    ups = rng.normal(size=(9, nb, nb, nb, nn, nn)) + 1j * rng.normal(size=(9, nb, nb, nb, nn, nn))
+    ups[8] = np.abs(ups[8]) + 5.0          # a positive normalisation
+    trip = np.array([[0, 1, 2], [2, 2, 2], [1, 0, 0], [0, 1, 2]])
+    g, n = oracle.natural_components_triplets(ups, nphi, trip)
+    G, N = oracle.natural_components(ups, nphi)
+    for k, (a, b, c) in enumerate(trip):
+        assert np.array_equal(n[k], N[a, b, c])
+        assert np.array_equal(g[:, k], G[:, a, b, c])
