@@ -23,8 +23,20 @@ __device__ inline void ang_int(int m, int a, int nphi, double& re, double& im) {
   im = -(ch - cl) / m;
 }
 
+// table[k][a] = I_{k - nmax}(Phi_a), complex
+__global__ void nat_table(int nmax, int nphi, double* table) {
+  const int nn = 2 * nmax + 1;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nn * nphi; t += gridDim.x * blockDim.x) {
+    double re, im;
+    ang_int(t / nphi - nmax, t % nphi, nphi, re, im);
+    table[2 * t] = re;
+    table[2 * t + 1] = im;
+  }
+}
+
 // tmp[q][a][n3] = sum_n2 ups[q][n2][n3] I_n2(a),  q = (mu, b1, b2, b3)
-__global__ void nat_pass1(const double* ups, int64_t nq, int nmax, int nphi, double* tmp) {
+__global__ void nat_pass1(const double* ups, int64_t nq, int nmax, int nphi, const double* table,
+                          double* tmp) {
   const int nn = 2 * nmax + 1;
   const int64_t total = nq * nphi * nn;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
@@ -34,8 +46,7 @@ __global__ void nat_pass1(const double* ups, int64_t nq, int nmax, int nphi, dou
     const int64_t q = t / ((int64_t)nn * nphi);
     double sr = 0.0, si = 0.0;
     for (int k = 0; k < nn; ++k) {
-      double ir, ii;
-      ang_int(k - nmax, a, nphi, ir, ii);
+      const double ir = table[2 * (k * nphi + a)], ii = table[2 * (k * nphi + a) + 1];
       const double ur = ups[2 * ((q * nn + k) * nn + n3)], ui = ups[2 * ((q * nn + k) * nn + n3) + 1];
       sr += ur * ir - ui * ii;
       si += ur * ii + ui * ir;
@@ -46,7 +57,8 @@ __global__ void nat_pass1(const double* ups, int64_t nq, int nmax, int nphi, dou
 }
 
 // out[q][a][b] = (2 pi)^-2 sum_n3 tmp[q][a][n3] I_n3(b)
-__global__ void nat_pass2(const double* tmp, int64_t nq, int nmax, int nphi, double* out) {
+__global__ void nat_pass2(const double* tmp, int64_t nq, int nmax, int nphi, const double* table,
+                          double* out) {
   const int nn = 2 * nmax + 1;
   const double s = 1.0 / (4.0 * M_PI * M_PI);
   const int64_t total = nq * nphi * nphi;
@@ -57,8 +69,7 @@ __global__ void nat_pass2(const double* tmp, int64_t nq, int nmax, int nphi, dou
     const int64_t q = t / ((int64_t)nphi * nphi);
     double sr = 0.0, si = 0.0;
     for (int k = 0; k < nn; ++k) {
-      double ir, ii;
-      ang_int(k - nmax, b, nphi, ir, ii);
+      const double ir = table[2 * (k * nphi + b)], ii = table[2 * (k * nphi + b) + 1];
       const int64_t o = (q * nphi + a) * nn + k;
       const double ur = tmp[2 * o], ui = tmp[2 * o + 1];
       sr += ur * ir - ui * ii;
@@ -105,11 +116,17 @@ hipError_t natural_triplets(const double* ups, int nb, int nmax, int nphi, const
                             double* norm, hipStream_t s) {
   const int64_t nq = 9 * ntrip;
   const int64_t per_mu = ntrip * nphi * nphi;
+  double* table = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&table), (size_t)(2 * nmax + 1) * nphi * 16, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(nat_table, dim3(64), dim3(256), 0, s, nmax, nphi, table);
   hipLaunchKernelGGL(nat_gather, dim3(2048), dim3(256), 0, s, ups, nb, nmax, trip, ntrip, sel);
-  hipLaunchKernelGGL(nat_pass1, dim3(2048), dim3(256), 0, s, sel, nq, nmax, nphi, tmp);
-  hipLaunchKernelGGL(nat_pass2, dim3(2048), dim3(256), 0, s, tmp, nq, nmax, nphi, binned);
+  hipLaunchKernelGGL(nat_pass1, dim3(2048), dim3(256), 0, s, sel, nq, nmax, nphi, table, tmp);
+  hipLaunchKernelGGL(nat_pass2, dim3(2048), dim3(256), 0, s, tmp, nq, nmax, nphi, table, binned);
   hipLaunchKernelGGL(nat_divide, dim3(1024), dim3(256), 0, s, binned, per_mu, gamma, norm);
-  return hipGetLastError();
+  e = hipGetLastError();
+  (void)hipFreeAsync(table, s);
+  return e;
 }
 
 hipError_t natural_components(const double* ups, int nb, int nmax, int nphi, double* tmp,
@@ -118,16 +135,21 @@ hipError_t natural_components(const double* ups, int nb, int nmax, int nphi, dou
   const int64_t per_mu = (int64_t)nb * nb * nb * nphi * nphi;
   // the binned sums of all nine correlators go to a temporary; Gamma and
   // Nbar are formed from it
-  hipLaunchKernelGGL(nat_pass1, dim3(2048), dim3(256), 0, s, ups, nq, nmax, nphi, tmp);
-  hipError_t e = hipGetLastError();
+  double* table = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&table), (size_t)(2 * nmax + 1) * nphi * 16, s);
   if (e != hipSuccess) return e;
-  double* binned = nullptr;
-  e = hipMallocAsync(reinterpret_cast<void**>(&binned), (size_t)(9 * per_mu) * 16, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(nat_pass2, dim3(2048), dim3(256), 0, s, tmp, nq, nmax, nphi, binned);
-  hipLaunchKernelGGL(nat_divide, dim3(1024), dim3(256), 0, s, binned, per_mu, gamma, norm);
+  hipLaunchKernelGGL(nat_table, dim3(64), dim3(256), 0, s, nmax, nphi, table);
+  hipLaunchKernelGGL(nat_pass1, dim3(2048), dim3(256), 0, s, ups, nq, nmax, nphi, table, tmp);
   e = hipGetLastError();
-  (void)hipFreeAsync(binned, s);
+  double* binned = nullptr;
+  if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&binned), (size_t)(9 * per_mu) * 16, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(nat_pass2, dim3(2048), dim3(256), 0, s, tmp, nq, nmax, nphi, table, binned);
+    hipLaunchKernelGGL(nat_divide, dim3(1024), dim3(256), 0, s, binned, per_mu, gamma, norm);
+    e = hipGetLastError();
+    (void)hipFreeAsync(binned, s);
+  }
+  (void)hipFreeAsync(table, s);
   return e;
 }
 
