@@ -11,3 +11,5 @@ from .natural import (angular_integrals, binned_from_multipoles, natural_compone
                       natural_components_triplets)
 from .nthorder import (beta_matrix, arg_coefficients, norm_coefficients, upsilon_n, upsilon3,
                        brute_upsilon3)
+from .tree import (tree_levels, reduced_catalogue, reduced_hierarchy, tree_centre_multipoles,
+                   upsilon_tree, brute_tree_upsilon)
