@@ -146,6 +146,31 @@ fpcf4_status estimate_3pcf_multipoles(const fpcf4_catalogue *cat,
                                       const fpcf4_options *opts,
                                       double *upsilon3, int32_t out_mem);
 
+/* Tree approximation of the per-centre multipoles (Sect. 3, practical
+ * implementation): a hierarchy of grids of cell side delta1 * 2^(d-1),
+ * d = 1..nlevels; every non-empty cell becomes one pseudo-galaxy at its
+ * w-weighted centre of mass carrying the cell sums of w gamma, w and of the
+ * multiple-counting weights; a radial bin takes its neighbours from the
+ * coarsest grid with edges[b] / Delta_d >= rmin, or from the galaxies when
+ * none qualifies.  Centres remain the galaxies.  Grids are anchored at the
+ * catalogue's minimum x and y. */
+typedef struct {
+  int32_t nlevels;             /* 1 .. 4                                      */
+  int32_t reserved;
+  double delta1;               /* finest cell side (arcmin), > 0              */
+  double rmin;                 /* >= 2                                        */
+} fpcf4_tree;
+
+/* estimate_4pcf_multipoles with the tree approximation (same output).
+ * Mixed precisions only (FPCF4_E_UNSUPPORTED for FPCF4_FP64); invalid tree
+ * parameters give FPCF4_E_INVALID_ARG.  With no bin qualifying for a grid
+ * the result equals estimate_4pcf_multipoles. */
+fpcf4_status estimate_4pcf_multipoles_tree(const fpcf4_catalogue *cat,
+                                           const fpcf4_bins *bins,
+                                           const fpcf4_options *opts,
+                                           const fpcf4_tree *tree,
+                                           double *upsilon, int32_t out_mem);
+
 /* Stage (a) only, for parity checks (Sect. 3.1: the per-centre blocks G_n and
  * W_n "defined as in P24", read as G_k = sum_j w_j gamma_j e^{+ik phi_ij} and
  * W_k = sum_j w_j e^{+ik phi_ij} over neighbours j in the bin).

@@ -102,20 +102,28 @@ class _Marshal:
 
 def estimate_4pcf_multipoles(x, y, g1, g2, w, edges, nmax: int, precision="fp64",
                              subtract_degenerate: bool = True, centers=None,
-                             tile_centers: int = 0, stream=None, out=None):
+                             tile_centers: int = 0, stream=None, out=None, tree=None):
     """Upsilon_{mu,(n2,n3)}(T1,T2,T3), mu = 0..7, and N (index 8) as a
     complex128 array [9, nb, nb, nb, 2nmax+1, 2nmax+1] (NumPy for host inputs,
-    a torch tensor on the inputs' device for device inputs)."""
+    a torch tensor on the inputs' device for device inputs).
+    tree = (delta1, nlevels, rmin) selects the tree approximation (reduced
+    catalogues on grids delta1 * 2^(d-1); mixed precisions only)."""
     m = _Marshal(x, y, g1, g2, w, edges, nmax, precision, subtract_degenerate, centers,
                  tile_centers, stream)
     shape = output_shape(m.nbins, m.nmax)
+    if tree is not None:
+        delta1, nlevels, rmin = tree
+        t = _lib.Tree(int(nlevels), 0, float(delta1), float(rmin))
+        call = lambda ptr, mem: lib().estimate_4pcf_multipoles_tree(*m.refs(), C.byref(t), ptr, mem)
+    else:
+        call = lambda ptr, mem: lib().estimate_4pcf_multipoles(*m.refs(), ptr, mem)
     if m.device:
         import torch
         res = out if out is not None else torch.empty(shape, dtype=torch.complex128, device=m.torch_device)
-        check(lib().estimate_4pcf_multipoles(*m.refs(), C.c_void_p(res.data_ptr()), MEM_DEVICE))
+        check(call(C.c_void_p(res.data_ptr()), MEM_DEVICE))
         return res
     res = out if out is not None else np.empty(shape, dtype=np.complex128)
-    check(lib().estimate_4pcf_multipoles(*m.refs(), C.c_void_p(res.ctypes.data), MEM_HOST))
+    check(call(C.c_void_p(res.ctypes.data), MEM_HOST))
     return res
 
 

@@ -33,6 +33,11 @@ class Bins(C.Structure):
     _fields_ = [("nbins", C.c_int32), ("edges", C.c_void_p)]
 
 
+class Tree(C.Structure):
+    _fields_ = [("nlevels", C.c_int32), ("reserved", C.c_int32),
+                ("delta1", C.c_double), ("rmin", C.c_double)]
+
+
 class Options(C.Structure):
     _fields_ = [("nmax", C.c_int32), ("precision", C.c_int32),
                 ("subtract_degenerate", C.c_int32), ("reserved", C.c_int32),
@@ -104,6 +109,9 @@ def lib():
                                             C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32,
                                             C.c_void_p]
     L.fpcf4_to_natural_triplets.restype = C.c_int32
+    L.estimate_4pcf_multipoles_tree.argtypes = [P(Catalogue), P(Bins), P(Options), P(Tree), C.c_void_p,
+                                                C.c_int32]
+    L.estimate_4pcf_multipoles_tree.restype = C.c_int32
     _lib = L
     return L
 
@@ -118,5 +126,5 @@ EXPORTED = [
     "fpcf4_request_create", "fpcf4_request_step", "fpcf4_request_finalize",
     "fpcf4_request_destroy", "fpcf4_last_error", "fpcf4_version", "fpcf4_output_elems",
     "fpcf4_profile_enable", "fpcf4_profile_read", "estimate_3pcf_multipoles", "fpcf4_output3_elems",
-    "fpcf4_to_natural_triplets",
+    "fpcf4_to_natural_triplets", "estimate_4pcf_multipoles_tree",
 ]

@@ -72,6 +72,11 @@ struct PlanInfo {
       o_pairs, o_part, o_ups, o_bpart, o_corr, o_cpart, o_acc3, o_part3, o_xg, o_xw, o_counts,
       o_aos, o_region;
   int bslices = 1;             // centre slices of the contraction (partials when > 1)
+  // tree approximation
+  int tree_levels = 0;                      // grids in use (highest level of any bin)
+  double tree_delta1 = 0.0;
+  int8_t level[FPCF4_NBINS_SUPPORTED] = {};  // per bin: 0 = galaxies, d = grid d
+  size_t o_rgal[TREE_LEVELS_MAX] = {}, o_rcell[TREE_LEVELS_MAX] = {}, t_red = 0;
   size_t region = 0;           // records of one tile, or create-time temporaries
   // create-time temporaries inside the region
   size_t t_raw, t_key_a, t_key_b, t_idx_a, t_idx_b, t_inv, t_sort, t_cent64;
@@ -108,9 +113,29 @@ fpcf4_status validate_common(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
 }
 
 fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
-                       const fpcf4_options* opts, PlanInfo& P, int order = 4, int m3 = 0) {
+                       const fpcf4_options* opts, PlanInfo& P, int order = 4, int m3 = 0,
+                       const fpcf4_tree* tree = nullptr) {
   fpcf4_status st = validate_common(cat, bins, opts);
   if (st != FPCF4_OK) return st;
+  if (tree) {
+    if (tree->nlevels < 1 || tree->nlevels > TREE_LEVELS_MAX)
+      return fail(FPCF4_E_INVALID_ARG, "tree levels %d not in 1..%d", tree->nlevels, TREE_LEVELS_MAX);
+    if (!(tree->delta1 > 0.0) || !std::isfinite(tree->delta1))
+      return fail(FPCF4_E_INVALID_ARG, "tree delta1 must be > 0");
+    if (!(tree->rmin >= 2.0) || !std::isfinite(tree->rmin))
+      return fail(FPCF4_E_INVALID_ARG, "tree rmin must be >= 2");
+    if (opts->precision == FPCF4_FP64)
+      return fail(FPCF4_E_UNSUPPORTED, "the tree approximation runs in the mixed paths only");
+    // per bin the coarsest grid with edges[b] / Delta_d >= rmin
+    P.tree_delta1 = tree->delta1;
+    for (int b = 0; b < bins->nbins; ++b) {
+      int best = 0;
+      for (int d = 1; d <= tree->nlevels; ++d)
+        if (bins->edges[b] / (tree->delta1 * std::ldexp(1.0, d - 1)) >= tree->rmin) best = d;
+      P.level[b] = (int8_t)best;
+      P.tree_levels = std::max(P.tree_levels, best);
+    }
+  }
   P.order = order;
   P.m3 = m3;
   P.n = cat->n;
@@ -157,6 +182,10 @@ fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   P.o_cpart = take(P.corr_bytes * CORR_SLICES);
   P.o_acc3 = take(P.acc3_bytes);
   P.o_part3 = take(P.acc3_bytes * THREE_SLICES);
+  for (int d = 1; d <= P.tree_levels; ++d) {
+    P.o_rgal[d - 1] = take(n * sizeof(GalR<float>));
+    P.o_rcell[d - 1] = take((P.ncell_cap + 1) * 4);
+  }
   P.o_xg = take((size_t)P.ldc * 2 * P.tsize);
   P.o_xw = take((size_t)P.ldc * P.tsize);
   P.o_aos = take((size_t)P.tile * rec_per_centre);
@@ -172,6 +201,7 @@ fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   P.t_inv = ttake(n * 4);
   P.t_cent64 = ttake((size_t)std::max<int64_t>(P.ncent, 1) * 8);
   P.t_sort = ttake(P.sort_tmp);
+  if (P.tree_levels > 0) P.t_red = ttake(reduced_scratch_bytes(n));
   P.region = std::max(t, up((size_t)P.ldc * rec_per_centre));
   P.o_region = take(P.region);
   P.total = off;
@@ -220,9 +250,9 @@ namespace {
 
 fpcf4_status request_init(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
                           const fpcf4_options* opts, void* wsp, size_t bytes, fpcf4_request* R,
-                          int order = 4, int m3 = 0) {
+                          int order = 4, int m3 = 0, const fpcf4_tree* tree = nullptr) {
   PlanInfo& P = R->P;
-  fpcf4_status st = make_plan(cat, bins, opts, P, order, m3);
+  fpcf4_status st = make_plan(cat, bins, opts, P, order, m3, tree);
   if (st != FPCF4_OK) return st;
   if (!wsp) return fail(FPCF4_E_INVALID_ARG, "null workspace");
   if (reinterpret_cast<uintptr_t>(wsp) % ALIGN) return fail(FPCF4_E_INVALID_ARG, "workspace not 256-byte aligned");
@@ -319,6 +349,13 @@ fpcf4_status request_init(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
     HIPCHK(cells_centre_order(key_b, n, g, key_a, reinterpret_cast<uint32_t*>(inv), idx_a, centres,
                               sort_tmp, P.sort_tmp, s));
   }
+  // reduced catalogues of the tree approximation, on the same search grid
+  for (int d = 1; d <= P.tree_levels; ++d) {
+    int64_t m = 0;
+    HIPCHK(reduced_build(x, y, g1, g2, w, n, bb[0], bb[2], bb[1], bb[3],
+                         P.tree_delta1 * std::ldexp(1.0, d - 1), g, reg + P.t_red,
+                         R->ws + P.o_rgal[d - 1], R->at<int32_t>(P.o_rcell[d - 1]), &m, s));
+  }
   HIPCHK(hipStreamSynchronize(s));
   return FPCF4_OK;
 }
@@ -363,6 +400,12 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
   a.counts = R->want_counts ? R->at<int32_t>(P.o_counts) : nullptr;
   a.work_counter = counters;
   a.pairs = R->at<unsigned long long>(P.o_pairs);
+  a.bin_mask = (P.nb >= 32) ? 0xffffffffu : ((1u << P.nb) - 1u);
+  for (int b = 0; b < P.nb; ++b) a.level[b] = P.level[b];
+  for (int d = 1; d <= P.tree_levels; ++d) {
+    a.rgal[d - 1] = R->ws + P.o_rgal[d - 1];
+    a.rcell[d - 1] = R->at<int32_t>(P.o_rcell[d - 1]);
+  }
   int nlaunch = 0;
   if (P.precision == FPCF4_FP64) HIPCHK(launch_stage_a<double>(P.nmax, a, s, &nlaunch, evs[1]));
   else HIPCHK(launch_stage_a<float>(P.nmax, a, s, &nlaunch, evs[1]));
@@ -538,6 +581,29 @@ fpcf4_status estimate_4pcf_multipoles(const fpcf4_catalogue* cat, const fpcf4_bi
   for (int64_t t = 0; st == FPCF4_OK && t < P.ntiles; ++t) st = fpcf4_request_step(R, t);
   if (st == FPCF4_OK) st = fpcf4_request_finalize(R, upsilon, out_mem);
   fpcf4_request_destroy(R);
+  hipError_t e = hipFreeAsync(ws, s);
+  if (st == FPCF4_OK && e != hipSuccess) return fail(FPCF4_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));
+  return st;
+}
+
+fpcf4_status estimate_4pcf_multipoles_tree(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
+                                           const fpcf4_options* opts, const fpcf4_tree* tree,
+                                           double* upsilon, int32_t out_mem) {
+  if (!upsilon || !tree) return fail(FPCF4_E_INVALID_ARG, "null argument");
+  if (out_mem != FPCF4_MEM_HOST && out_mem != FPCF4_MEM_DEVICE) return fail(FPCF4_E_INVALID_ARG, "out_mem %d", out_mem);
+  PlanInfo P;
+  fpcf4_status st = make_plan(cat, bins, opts, P, 4, 0, tree);
+  if (st != FPCF4_OK) return st;
+  setup_pool();
+  hipStream_t s = static_cast<hipStream_t>(opts->stream);
+  void* ws = nullptr;
+  HIPCHK(hipMallocAsync(&ws, P.total, s));
+  fpcf4_request* R = new (std::nothrow) fpcf4_request();
+  if (!R) st = fail(FPCF4_E_OUT_OF_MEMORY, "host allocation failed");
+  if (st == FPCF4_OK) st = request_init(cat, bins, opts, ws, P.total, R, 4, 0, tree);
+  for (int64_t t = 0; st == FPCF4_OK && t < P.ntiles; ++t) st = request_step(R, t, true);
+  if (st == FPCF4_OK) st = fpcf4_request_finalize(R, upsilon, out_mem);
+  delete R;
   hipError_t e = hipFreeAsync(ws, s);
   if (st == FPCF4_OK && e != hipSuccess) return fail(FPCF4_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));
   return st;

@@ -11,6 +11,8 @@
 //                   centre list (sorted by it) visits space in compact blocks
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+
 #include "fpcf4_internal.hpp"
 
 namespace fpcf4 {
@@ -200,6 +202,204 @@ hipError_t cells_centre_order(const uint32_t* skey, int64_t n, const Grid& g, ui
   hipLaunchKernelGGL(morton_kernel, dim3(grid1d(n)), dim3(256), 0, s, skey, n, g.ncx, mkey_a, idx_a);
   size_t tb = sort_tmp_bytes;
   return hipcub::DeviceRadixSort::SortPairs(sort_tmp, tb, mkey_a, mkey_b, idx_a, out, (int)n, 0, 32, s);
+}
+
+// ---------------------------------------------------------------------------
+// Reduced catalogues (tree approximation): one pseudo-galaxy per non-empty
+// cell of side delta anchored at (x0, y0), at the cell's w-weighted centre
+// of mass, carrying the cell sums of every family weight.
+// ---------------------------------------------------------------------------
+constexpr int RED_FIELDS = 14;   // x, y, a, b, c, d, e, v, w, p3, q3, ea, eb, u
+
+__global__ void rkey_kernel(const double* x, const double* y, int64_t n, double x0, double y0,
+                            double delta, int64_t nx, int64_t ny, uint64_t* key, int32_t* idx) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t ix = (int64_t)floor((x[i] - x0) / delta);
+    int64_t iy = (int64_t)floor((y[i] - y0) / delta);
+    ix = ix < 0 ? 0 : (ix >= nx ? nx - 1 : ix);
+    iy = iy < 0 ? 0 : (iy >= ny ? ny - 1 : iy);
+    key[i] = (uint64_t)iy * (uint64_t)nx + (uint64_t)ix;
+    idx[i] = (int32_t)i;
+  }
+}
+
+__global__ void rhead_kernel(const uint64_t* key, int64_t n, int32_t* head) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    head[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+}
+
+// segstart[s] = first sorted position of cell segment s; segstart[m] = n
+__global__ void rsegstart_kernel(const int32_t* head, const int32_t* segid, int64_t n,
+                                 int32_t* segstart) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (head[i]) segstart[segid[i]] = (int32_t)i;
+    if (i == n - 1) segstart[segid[i] + head[i]] = (int32_t)n;
+  }
+}
+
+// Cell sums in binary64, galaxies of a cell in catalogue order (the sort is
+// stable), products and sums rounded separately; pd[field][m].
+__global__ void rsum_kernel(const double* x, const double* y, const double* g1, const double* g2,
+                            const double* w, const int32_t* perm, const int32_t* head,
+                            const int32_t* segid, const int32_t* segstart, int64_t n,
+                            double* pd) {
+#pragma clang fp contract(off)
+  const int64_t m = (int64_t)segid[n - 1] + head[n - 1];
+  for (int64_t sg = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; sg < m;
+       sg += (int64_t)gridDim.x * blockDim.x) {
+    double W = 0, WX = 0, WY = 0, SX = 0, SY = 0, A = 0, B = 0, C = 0, D = 0, E = 0, V = 0;
+    double P3 = 0, Q3 = 0, EA = 0, EB = 0, U = 0;
+    const int32_t t0 = segstart[sg], t1 = segstart[sg + 1];
+    for (int32_t t = t0; t < t1; ++t) {
+      const int32_t p = perm[t];
+      const double wv = w[p], xv = x[p], yv = y[p];
+      const double gr = wv * g1[p], gi = wv * g2[p];
+      const double cr = gr * gr - gi * gi, ci = 2.0 * gr * gi;
+      const double ab = gr * gr + gi * gi;
+      W += wv;
+      WX += wv * xv;
+      WY += wv * yv;
+      SX += xv;
+      SY += yv;
+      A += gr;
+      B += gi;
+      C += cr;
+      D += ci;
+      E += ab;
+      V += wv * wv;
+      P3 += cr * gr - ci * gi;
+      Q3 += cr * gi + ci * gr;
+      EA += ab * gr;
+      EB += ab * gi;
+      U += wv * wv * wv;
+    }
+    const double cnt = (double)(t1 - t0);
+    const double f[RED_FIELDS] = {W != 0.0 ? WX / W : SX / cnt, W != 0.0 ? WY / W : SY / cnt,
+                                  A, B, C, D, E, V, W, P3, Q3, EA, EB, U};
+#pragma unroll
+    for (int k = 0; k < RED_FIELDS; ++k) pd[k * n + sg] = f[k];
+  }
+}
+
+__global__ void rgather_kernel(const double* pd, int64_t ldp, const int32_t* perm, int64_t m,
+                               GalR<float>* out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = perm[i];
+    GalR<float> r;
+    r.x = pd[0 * ldp + p];
+    r.y = pd[1 * ldp + p];
+    r.a = (float)pd[2 * ldp + p];
+    r.b = (float)pd[3 * ldp + p];
+    r.c = (float)pd[4 * ldp + p];
+    r.d = (float)pd[5 * ldp + p];
+    r.e = (float)pd[6 * ldp + p];
+    r.v = (float)pd[7 * ldp + p];
+    r.w = (float)pd[8 * ldp + p];
+    r.p3 = (float)pd[9 * ldp + p];
+    r.q3 = (float)pd[10 * ldp + p];
+    r.ea = (float)pd[11 * ldp + p];
+    r.eb = (float)pd[12 * ldp + p];
+    r.u = (float)pd[13 * ldp + p];
+    out[i] = r;
+  }
+}
+
+namespace {
+struct RedLayout {
+  size_t k64a, k64b, ia, ib, head, segid, segstart, pd, ka, kb, pa, pb, tmp, tmp_bytes, total;
+};
+RedLayout red_layout(int64_t n) {
+  const int64_t nn = n > 0 ? n : 1;
+  auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+  size_t t64 = 0, t32 = 0, tsc = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, t64, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                           (const int32_t*)nullptr, (int32_t*)nullptr, (int)nn, 0, 64);
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, t32, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           (const int32_t*)nullptr, (int32_t*)nullptr, (int)nn, 0, 32);
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tsc, (const int32_t*)nullptr, (int32_t*)nullptr, (int)nn);
+  RedLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t b) { size_t r = o; o += up(b); return r; };
+  L.k64a = take(nn * 8);
+  L.k64b = take(nn * 8);
+  L.ia = take(nn * 4);
+  L.ib = take(nn * 4);
+  L.head = take(nn * 4);
+  L.segid = take(nn * 4);
+  L.segstart = take((nn + 1) * 4);
+  L.pd = take((size_t)RED_FIELDS * nn * 8);
+  L.ka = take(nn * 4);
+  L.kb = take(nn * 4);
+  L.pa = take(nn * 4);
+  L.pb = take(nn * 4);
+  L.tmp_bytes = std::max(t64, std::max(t32, tsc)) + 4096;
+  L.tmp = take(L.tmp_bytes);
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+size_t reduced_scratch_bytes(int64_t n) { return red_layout(n).total; }
+
+hipError_t reduced_build(const double* x, const double* y, const double* g1, const double* g2,
+                         const double* w, int64_t n, double x0, double y0, double xmax, double ymax,
+                         double delta, const Grid& g, void* scratch, void* gal_out,
+                         int32_t* cell_start, int64_t* m_out, hipStream_t s) {
+  *m_out = 0;
+  if (n <= 0) return hipSuccess;
+  const RedLayout L = red_layout(n);
+  char* sc = static_cast<char*>(scratch);
+  auto at = [&](size_t o) { return sc + o; };
+  uint64_t* k64a = reinterpret_cast<uint64_t*>(at(L.k64a));
+  uint64_t* k64b = reinterpret_cast<uint64_t*>(at(L.k64b));
+  int32_t* ia = reinterpret_cast<int32_t*>(at(L.ia));
+  int32_t* ib = reinterpret_cast<int32_t*>(at(L.ib));
+  int32_t* head = reinterpret_cast<int32_t*>(at(L.head));
+  int32_t* segid = reinterpret_cast<int32_t*>(at(L.segid));
+  int32_t* segstart = reinterpret_cast<int32_t*>(at(L.segstart));
+  double* pd = reinterpret_cast<double*>(at(L.pd));
+  uint32_t* ka = reinterpret_cast<uint32_t*>(at(L.ka));
+  uint32_t* kb = reinterpret_cast<uint32_t*>(at(L.kb));
+  int32_t* pa = reinterpret_cast<int32_t*>(at(L.pa));
+  int32_t* pb = reinterpret_cast<int32_t*>(at(L.pb));
+  void* tmp = at(L.tmp);
+  const int64_t nx = (int64_t)floor((xmax - x0) / delta) + 1;
+  const int64_t ny = (int64_t)floor((ymax - y0) / delta) + 1;
+  if (nx <= 0 || ny <= 0 || (double)nx * (double)ny >= 1.8e19) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rkey_kernel, dim3(grid1d(n)), dim3(256), 0, s, x, y, n, x0, y0, delta, nx, ny, k64a, ia);
+  size_t tb = L.tmp_bytes;
+  int kbits = 1;
+  while (kbits < 64 && (1ull << kbits) <= (uint64_t)nx * (uint64_t)ny) ++kbits;
+  hipError_t e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, k64a, k64b, ia, ib, (int)n, 0, kbits, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rhead_kernel, dim3(grid1d(n)), dim3(256), 0, s, k64b, n, head);
+  tb = L.tmp_bytes;
+  e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, head, segid, (int)n, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rsegstart_kernel, dim3(grid1d(n)), dim3(256), 0, s, head, segid, n, segstart);
+  hipLaunchKernelGGL(rsum_kernel, dim3(grid1d(n)), dim3(256), 0, s, x, y, g1, g2, w, ib, head, segid,
+                     segstart, n, pd);
+  int32_t hm[2] = {0, 0};
+  e = hipMemcpyAsync(&hm[0], segid + (n - 1), 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hm[1], head + (n - 1), 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  const int64_t m = (int64_t)hm[0] + hm[1];
+  // search-grid order of the pseudo-galaxies, cell starts, records
+  const int64_t ncells = (int64_t)g.ncx * g.ncy;
+  hipLaunchKernelGGL(key_kernel, dim3(grid1d(m)), dim3(256), 0, s, pd, pd + n, m, g, ka, pa);
+  tb = L.tmp_bytes;
+  e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, ka, kb, pa, pb, (int)m, 0, bits_for((uint64_t)ncells), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(starts_kernel, dim3(grid1d(m + 1)), dim3(256), 0, s, kb, m, ncells, cell_start);
+  hipLaunchKernelGGL(rgather_kernel, dim3(grid1d(m)), dim3(256), 0, s, pd, n, pb, m,
+                     reinterpret_cast<GalR<float>*>(gal_out));
+  *m_out = m;
+  return hipGetLastError();
 }
 
 hipError_t cells_map_centres(const int64_t* centres, int64_t nc, const int32_t* inv, int32_t* out,

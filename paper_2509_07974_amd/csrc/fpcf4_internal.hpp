@@ -83,6 +83,18 @@ template <> struct alignas(16) Gal<float> { double x, y; float a, b, w, pad; };
 template <> struct alignas(16) Gal<double> { double x, y, a, b, w, pad; };
 static_assert(sizeof(Gal<float>) == 32 && sizeof(Gal<double>) == 48, "galaxy record size");
 
+// One pseudo-galaxy of a reduced catalogue (tree approximation): the cell's
+// w-weighted centre of mass and the cell sums of every per-galaxy family
+// weight (Re/Im w g, Re/Im (w g)^2, |w g|^2, w^2, w, Re/Im (w g)^3,
+// Re/Im |w g|^2 w g, w^3), each rounded once from its binary64 sum.
+template <typename T> struct alignas(16) GalR;
+template <> struct alignas(16) GalR<float> {
+  double x, y;
+  float a, b, c, d, e, v, w, p3, q3, ea, eb, u;
+};
+static_assert(sizeof(GalR<float>) == 64, "pseudo-galaxy record size");
+constexpr int TREE_LEVELS_MAX = 4;
+
 // Sorted catalogue on the device.
 struct SortedCat {
   int64_t n;
@@ -107,7 +119,23 @@ struct StageAArgs {
   int32_t* counts;          // [ncent][nb] or null
   int32_t* work_counter;    // dynamic centre scheduling counters, one per XCD
   unsigned long long* pairs;  // in-bin pair counter (may be null)
+  uint32_t bin_mask;        // bins to accumulate (bit b); the rest are left alone
+  // tree approximation: bins with level[b] = d >= 1 take their neighbours
+  // from reduced catalogue d (same search grid as cat); 0 = discrete
+  int8_t level[FPCF4_NBINS_SUPPORTED];
+  const void* rgal[TREE_LEVELS_MAX];         // GalR<float>, sorted by search cell
+  const int32_t* rcell[TREE_LEVELS_MAX];     // their cell starts
 };
+
+// Reduced catalogue of cell side delta anchored at (x0, y0) (tree
+// approximation): pseudo-galaxies sorted on the search grid g, with cell
+// starts.  Scratch is caller-provided (reduced_scratch_bytes); returns the
+// number of pseudo-galaxies in *m (host, after a stream synchronisation).
+size_t reduced_scratch_bytes(int64_t n);
+hipError_t reduced_build(const double* x, const double* y, const double* g1, const double* g2,
+                         const double* w, int64_t n, double x0, double y0, double xmax, double ymax,
+                         double delta, const Grid& g, void* scratch, void* gal_out,
+                         int32_t* cell_start, int64_t* m, hipStream_t s);
 
 // stage (a) launcher, T = double or float: the pair-multipole kernel, then
 // the relayout of its records to centre-contiguous rows.  Returns the number

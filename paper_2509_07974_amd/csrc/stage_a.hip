@@ -34,6 +34,8 @@
 //    (log2 64 levels, halving the live values per level), so each lane ends
 //    with complete sums of its own units; the binary32 variant folds into
 //    binary64 masters every few batches (blocked summation).
+#include <type_traits>
+
 #include "fpcf4_internal.hpp"
 
 namespace fpcf4 {
@@ -335,6 +337,7 @@ template <typename T> struct alignas(2 * sizeof(T)) Q2 { T x, y; };
 template <typename T> struct Nb {
   T zr, zi, a, b, c, d, e, v, w;
   T sr, si;   // z^K0 of the consuming pass, when the binning lane formed it
+  T p3, q3, ea, eb, u;   // triple-block weights of a pseudo-galaxy (reduced catalogues)
 };
 
 // binary32 passes take their first power z^K0 from the ring (formed once per
@@ -343,9 +346,9 @@ template <typename T> constexpr bool kRingStarts = sizeof(T) == 4;
 
 // Add one neighbour to the units of one pass.  Lanes with valid == false
 // add nothing.
-template <typename T, int N, int K0, int K1, bool P0, int NUO>
+template <typename T, int N, int K0, int K1, bool P0, int NUO, bool RED>
 __device__ __forceinline__ void add_pair(T* acc, bool valid, Nb<T> q) {
-  if (!valid) q = Nb<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+  if (!valid) q = Nb<T>{};
   T val[NF];
   val[FA] = q.a;
   val[FB] = q.b;
@@ -369,9 +372,11 @@ __device__ __forceinline__ void add_pair(T* acc, bool valid, Nb<T> q) {
     const T z2r = zr * zr - zi * zi, z2i = T(2) * zr * zi;
     const T z4r = z2r * z2r - z2i * z2i, z4i = T(2) * z2r * z2i;
     const T z8r = z4r * z4r - z4i * z4i, z8i = T(2) * z4r * z4i;
-    const T p3 = q.c * q.a - q.d * q.b;   // Re (w g)^3
-    const T q3 = q.c * q.b + q.d * q.a;   // Im (w g)^3
-    const T ea = q.e * q.a, eb = q.e * q.b;
+    // per galaxy: Re/Im (w g)^3 and |w g|^2 w g from w g; a pseudo-galaxy
+    // carries the cell sums of these weights
+    const T p3 = RED ? q.p3 : q.c * q.a - q.d * q.b;
+    const T q3 = RED ? q.q3 : q.c * q.b + q.d * q.a;
+    const T ea = RED ? q.ea : q.e * q.a, eb = RED ? q.eb : q.e * q.b;
     acc[NUO + 0] += p3 * z8r;
     acc[NUO + 1] += p3 * z8i;
     acc[NUO + 2] += q3 * z8r;
@@ -386,7 +391,7 @@ __device__ __forceinline__ void add_pair(T* acc, bool valid, Nb<T> q) {
     acc[NUO + 11] += eb * z4i;
     acc[NUO + 12] += ea;
     acc[NUO + 13] += eb;
-    acc[NUO + 14] += q.w * q.v;
+    acc[NUO + 14] += RED ? q.u : q.w * q.v;
   }
 }
 
@@ -415,7 +420,7 @@ __host__ __device__ constexpr int ring_cap(int w) {
   return c;
 }
 
-template <typename T, int W, int NMX> struct Shared {
+template <typename T, int W, int NMX, bool RED> struct Shared {
   static constexpr int CAP = ring_cap(W);
   // ring of in-bin neighbours (z, a, b | c, d, e, v | w); the entries of a
   // round are appended in wave order, so a batch is 64 consecutive slots
@@ -423,6 +428,8 @@ template <typename T, int W, int NMX> struct Shared {
   Q4<T> q1[CAP];
   T qw[CAP];
   Q2<T> qk[kRingStarts<T> && W > 1 ? W - 1 : 1][kRingStarts<T> && W > 1 ? CAP : 1];  // z^K0 of passes 1..W-1
+  Q4<T> q2[RED ? CAP : 1];  // pseudo-galaxies: (w g)^3, |w g|^2 w g cell sums
+  T qu[RED ? CAP : 1];      // pseudo-galaxies: w^3 cell sum
   double stage[W][NMX * 64];  // per-wave epilogue staging of the binary64 sums
   int rows[2][5][64];       // row table: s1, l1, s2, row length, inclusive prefix
   int cnt[W];               // in-bin count of each wave's chunk in this round
@@ -453,10 +460,12 @@ __device__ __forceinline__ void put_starts(SH& sh, unsigned slot, T zr, T zi, T 
 // for the next round; the last one of a bin is added as a partial batch.
 // The order is the same in every wave and every run (no atomics), so
 // results are reproducible bit for bit.
-template <typename T, int N, int PASS>
+template <typename T, int N, int PASS, bool RED>
 __device__ __forceinline__ void pass_body(const StageAArgs& a,
-                                          Shared<T, Conf<T, N>::W, Conf<T, N>::NMX>& sh,
+                                          Shared<T, Conf<T, N>::W, Conf<T, N>::NMX, RED>& sh,
                                           unsigned lane) {
+  // neighbour records: galaxies, or the pseudo-galaxies of reduced catalogues
+  using Rec = typename std::conditional<RED, GalR<T>, Gal<T>>::type;
   constexpr int W = Conf<T, N>::W;
   constexpr int K0 = Conf<T, N>::PP.k0[PASS];
   constexpr int K1 = Conf<T, N>::PP.k1[PASS];
@@ -474,7 +483,7 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
 
   const int xcd0 = blockIdx.x & 7;
   int xs = 0;          // pass 0: XCD cursor of the centre grab
-  constexpr unsigned CAP = Shared<T, W, Conf<T, N>::NMX>::CAP;
+  constexpr unsigned CAP = Shared<T, W, Conf<T, N>::NMX, RED>::CAP;
   unsigned head = 0, tail = 0;   // ring: appended / consumed neighbours
   auto fetch = [&](unsigned slot) -> Nb<T> {
     const Q4<T> u = sh.q0[slot];
@@ -485,7 +494,16 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
       sr = k.x;
       si = k.y;
     }
-    return Nb<T>{u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w, sh.qw[slot], sr, si};
+    Nb<T> q{u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w, sh.qw[slot], sr, si};
+    if constexpr (RED && PASS == 0) {
+      const Q4<T> t = sh.q2[slot];
+      q.p3 = t.x;
+      q.q3 = t.y;
+      q.ea = t.z;
+      q.eb = t.w;
+      q.u = sh.qu[slot];
+    }
+    return q;
   };
   unsigned tc = 0;     // centres so far (broadcast-slot parity)
   unsigned tt = 0;     // row tables so far (table parity)
@@ -520,8 +538,23 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
     const int i = a.centres[idx];
     const Gal<T> gi = gal[i];
     const double xi = gi.x, yi = gi.y;
+    if constexpr (P0 && !RED) {
+      if (lane == 0) {
+        // centre factors of this tile position
+        T* xg = reinterpret_cast<T*>(a.xg);
+        xg[2 * idx] = gi.a;
+        xg[2 * idx + 1] = gi.b;
+        reinterpret_cast<T*>(a.xw)[idx] = gi.w;
+        lane_xmax = fmaxf(lane_xmax, (float)fmax(fabs((double)gi.a), fabs((double)gi.b)));
+        lane_wxmax = fmaxf(lane_wxmax, (float)fabs((double)gi.w));
+      }
+    }
 
     for (int b = 0; b < nb; ++b) {
+      // bins of the other launch (discrete / reduced catalogues) are skipped
+      if (((a.bin_mask >> b) & 1u) == 0u) continue;
+      const Rec* __restrict__ ngal = reinterpret_cast<const Rec*>(RED ? a.rgal[a.level[b] - 1] : a.cat.gal);
+      const int32_t* __restrict__ cstart = RED ? a.rcell[a.level[b] - 1] : a.cat.cell_start;
       const double e2lo = a.e2[b], e2hi = a.e2[b + 1];
       // conservative culling radii and cell margin (binning itself is exact)
       const double rin = a.edges[b] * (1.0 - 1e-9);
@@ -574,7 +607,7 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
                   hx1 = imin(hx1, cx1);
                   if (hx0 > hx1) { hx0 = cx1 + 1; hx1 = cx1; }
                 }
-                const int32_t* cs = a.cat.cell_start + (int64_t)cy * g.ncx;
+                const int32_t* cs = cstart + (int64_t)cy * g.ncx;
                 s1 = cs[cx0];
                 l1 = cs[hx0] - s1;
                 s2 = cs[hx1 + 1];
@@ -626,15 +659,15 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
           return j;
         };
 
-        Gal<T> gn{};
+        Rec gn{};
         bool vn = false;
         if (PASS < nch) {
           const int j = locate(PASS);
-          if (j >= 0) { gn = gal[j]; vn = true; }
+          if (j >= 0) { gn = ngal[j]; vn = true; }
         }
         for (int r = 0; r < rounds; ++r) {
           // ---- bin this wave's chunk (binary64 r^2, no contraction)
-          const Gal<T> gc = gn;
+          const Rec gc = gn;
           const bool vc = vn;
           bool inb = false;
           double dx = 0.0, dy = 0.0;
@@ -652,7 +685,7 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
             vn = false;
             if (cn < nch) {
               const int j = locate(cn);
-              if (j >= 0) { gn = gal[j]; vn = true; }
+              if (j >= 0) { gn = ngal[j]; vn = true; }
             }
           }
           __syncthreads();
@@ -671,8 +704,13 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
             const T va = gc.a, vb = gc.b, vw = gc.w;
             const T zr = ex * inv, zi = ey * inv;
             sh.q0[slot] = Q4<T>{zr, zi, va, vb};
+            if constexpr (RED) {
+              sh.q1[slot] = Q4<T>{gc.c, gc.d, gc.e, gc.v};
+              sh.q2[slot] = Q4<T>{gc.p3, gc.q3, gc.ea, gc.eb};
+              sh.qu[slot] = gc.u;
+            }
             if constexpr (kRingStarts<T> && W > 1) put_starts<T, N, 1>(sh, slot, zr, zi, T(1), T(0));
-            sh.q1[slot] = Q4<T>{va * va - vb * vb, T(2) * va * vb, va * va + vb * vb, vw * vw};
+            if constexpr (!RED) sh.q1[slot] = Q4<T>{va * va - vb * vb, T(2) * va * vb, va * va + vb * vb, vw * vw};
             sh.qw[slot] = vw;
           }
           head += (unsigned)added;
@@ -680,7 +718,7 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
           __syncthreads();
           // ---- every pass adds the complete batches
           while (head - tail >= 64u) {
-            add_pair<T, N, K0, K1, P0, NUO>(acc, true, fetch((tail + lane) & (CAP - 1)));
+            add_pair<T, N, K0, K1, P0, NUO, RED>(acc, true, fetch((tail + lane) & (CAP - 1)));
             tail += 64u;
             if (++nblk == FOLD) {
               fold_all<T, NU, NM>(acc, mst, lane);
@@ -695,7 +733,7 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
         const bool valid = lane < head - tail;
         Nb<T> q{};
         if (valid) q = fetch((tail + lane) & (CAP - 1));
-        add_pair<T, N, K0, K1, P0, NUO>(acc, valid, q);
+        add_pair<T, N, K0, K1, P0, NUO, RED>(acc, valid, q);
         tail = head;
       }
       fold_all<T, NU, NM>(acc, mst, lane);
@@ -778,15 +816,6 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
           lane_wmax = fmaxf(lane_wmax, wmax);
         }
       }
-      if (P0 && b == 0 && lane == 0) {
-        // centre factors of this tile position
-        T* xg = reinterpret_cast<T*>(a.xg);
-        xg[2 * idx] = gi.a;
-        xg[2 * idx + 1] = gi.b;
-        reinterpret_cast<T*>(a.xw)[idx] = gi.w;
-        lane_xmax = fmaxf(lane_xmax, (float)fmax(fabs((double)gi.a), fabs((double)gi.b)));
-        lane_wxmax = fmaxf(lane_wxmax, (float)fabs((double)gi.w));
-      }
       if (P0) {
         if (a.counts != nullptr && lane == 0) a.counts[(int64_t)idx * nb + b] = cnt;
         wave_pairs += (unsigned long long)cnt;
@@ -807,21 +836,23 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
   }
 }
 
-template <typename T, int N, int P>
+template <typename T, int N, int P, bool RED>
 __device__ __forceinline__ void dispatch(int wv, const StageAArgs& a,
-                                         Shared<T, Conf<T, N>::W, Conf<T, N>::NMX>& sh, unsigned lane) {
+                                         Shared<T, Conf<T, N>::W, Conf<T, N>::NMX, RED>& sh, unsigned lane) {
   if constexpr (P < Conf<T, N>::W) {
-    if (wv == P) pass_body<T, N, P>(a, sh, lane);
-    else dispatch<T, N, P + 1>(wv, a, sh, lane);
+    if (wv == P) pass_body<T, N, P, RED>(a, sh, lane);
+    else dispatch<T, N, P + 1, RED>(wv, a, sh, lane);
   }
 }
 
-template <typename T, int N>
+// RED: neighbours from the reduced catalogues of the tree approximation
+// (binary32 only); the launch accumulates the bins of a.bin_mask.
+template <typename T, int N, bool RED>
 __global__ __launch_bounds__((64 * Conf<T, N>::W)) __attribute__((amdgpu_waves_per_eu(Conf<T, N>::EU))) void stage_a_kernel(StageAArgs a) {
-  __shared__ Shared<T, Conf<T, N>::W, Conf<T, N>::NMX> sh;
+  __shared__ Shared<T, Conf<T, N>::W, Conf<T, N>::NMX, RED> sh;
   // wave index as a scalar, so each wave branches to its own pass only
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  dispatch<T, N, 0>(wv, a, sh, lane_id());
+  dispatch<T, N, 0, RED>(wv, a, sh, lane_id());
 }
 
 // [centre][bin][entry] (as written per centre) -> [entry][bin][centre],
@@ -859,15 +890,14 @@ __global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ sr
   }
 }
 
-template <typename T, int N>
-hipError_t launch_n(const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t mid) {
-  constexpr int W = Conf<T, N>::W;
-  // persistent workgroups: as many as are resident at once, a multiple of
-  // the 8 XCDs (blocks are dealt round-robin to the XCDs)
+template <typename T, int N, bool RED>
+static int resident_blocks() {
+  // persistent workgroups: as many as are resident at once
   static int resident = -1;
   if (resident < 0) {
     int per_cu = 0, dev = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_a_kernel<T, N>, 64 * W, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_a_kernel<T, N, RED>,
+                                                     64 * Conf<T, N>::W, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -875,18 +905,53 @@ hipError_t launch_n(const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t
       ncu = 256;
     resident = per_cu * ncu;
   }
+  return resident;
+}
+
+template <typename T, int N, bool RED>
+static hipError_t launch_pairs(const StageAArgs& a, hipStream_t s) {
+  // a multiple of the 8 XCDs (blocks are dealt round-robin to the XCDs)
+  const int resident = resident_blocks<T, N, RED>();
   int nblocks = a.ncent < resident ? a.ncent : resident;
   nblocks = ((nblocks + 7) / 8) * 8;
   if (nblocks < 8) nblocks = 8;
-  hipLaunchKernelGGL((stage_a_kernel<T, N>), dim3(nblocks), dim3(64 * W), 0, s, a);
-  hipError_t e = hipGetLastError();
+  hipLaunchKernelGGL((stage_a_kernel<T, N, RED>), dim3(nblocks), dim3(64 * Conf<T, N>::W), 0, s, a);
+  return hipGetLastError();
+}
+
+// The discrete bins (level 0) in one launch and, with the tree
+// approximation, the bins on reduced catalogues in a second one (its own
+// scheduling counters); then the relayout of all records.
+template <typename T, int N>
+hipError_t launch_n(const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t mid) {
+  uint32_t exact = 0, red = 0;
+  for (int b = 0; b < a.nb; ++b) {
+    if (!((a.bin_mask >> b) & 1u)) continue;
+    if (a.level[b] > 0) red |= 1u << b;
+    else exact |= 1u << b;
+  }
+  *nlaunch = 0;
+  StageAArgs ae = a;
+  ae.bin_mask = exact;
+  hipError_t e = launch_pairs<T, N, false>(ae, s);
   if (e != hipSuccess) return e;
+  *nlaunch = 1;
+  if (red) {
+    if constexpr (sizeof(T) == 4) {
+      StageAArgs ar = a;
+      ar.bin_mask = red;
+      ar.work_counter = a.work_counter + 8;
+      if ((e = launch_pairs<T, N, true>(ar, s)) != hipSuccess) return e;
+      *nlaunch = 2;
+    } else {
+      return hipErrorInvalidValue;   // reduced catalogues are binary32 only
+    }
+  }
   if (mid != nullptr && (e = hipEventRecord(mid, s)) != hipSuccess) return e;
   const int mpc = make_layout(N).mpc;
   const dim3 grid((a.ncent + 63) / 64, a.nb, (mpc + 63) / 64);
   hipLaunchKernelGGL(transpose_kernel<T>, grid, dim3(256), 0, s, reinterpret_cast<const T*>(a.rec_aos),
                      reinterpret_cast<T*>(a.rec), a.ncent, a.nb, mpc, a.ldc);
-  *nlaunch = 1;
   return hipGetLastError();
 }
 

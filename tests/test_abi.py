@@ -128,3 +128,27 @@ def test_natural_triplets_invalid_arguments(nphi, trip, code):
                                        None, _lib.MEM_HOST, None)
     assert st == code
     assert lib.fpcf4_to_natural_triplets(None, 0, nb, nmax, 8, None, 0, None, None, 0, None) == -1
+
+
+@pytest.mark.parametrize("prec,tree,code", [
+    (1, (0.5, 0, 10.0), -1),     # no level
+    (1, (0.5, 5, 10.0), -1),     # more levels than supported
+    (1, (0.0, 2, 10.0), -1),     # zero cell side
+    (1, (0.5, 2, 1.5), -1),      # r_min below 2
+    (0, (0.5, 2, 10.0), -2),     # FP64 path
+])
+def test_tree_invalid_arguments_rejected(prec, tree, code):
+    from paper_2509_07974_amd import _lib
+    lib = ensure_built()
+    rng = np.random.default_rng(0)
+    n = 10
+    arrs = [rng.uniform(0, 10, n) for _ in range(5)]
+    cat = _lib.Catalogue(n, *[a.ctypes.data for a in arrs], _lib.MEM_HOST)
+    e = np.array([1.0, 2.0, 4.0])
+    bins = _lib.Bins(2, e.ctypes.data)
+    opts = _lib.Options(1, prec, 1, 0, None, 0, 0, None)
+    t = _lib.Tree(tree[1], 0, tree[0], tree[2])
+    out = np.zeros(9 * 8 * 9, complex)
+    st = lib.estimate_4pcf_multipoles_tree(C.byref(cat), C.byref(bins), C.byref(opts), C.byref(t),
+                                           C.c_void_p(out.ctypes.data), _lib.MEM_HOST)
+    assert st == code, lib.fpcf4_last_error()

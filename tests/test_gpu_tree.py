@@ -1,0 +1,120 @@
+"""GPU parity of the tree (reduced-catalogue) approximation against its FP64
+oracle, through the C ABI (mixed paths; bar 1e-5 normwise per correlator),
+plus the limits in which it must equal the discrete estimator."""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import rel_per_mu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import paper_2509_07974_amd as m
+    m.lib()
+    return m
+
+
+@functools.lru_cache(None)
+def c0():
+    cat, edges, nmax, _ = synth.workload("uniform-2k")
+    return cat, edges, nmax
+
+
+TREE = (0.5, 2, 10.0)     # 0.5' and 1' grids, r_min 10: bins -> levels [0, 0, 1, 2]
+
+
+@functools.lru_cache(None)
+def c0_tree_ref():
+    cat, edges, nmax = c0()
+    return oracle.upsilon_tree(*cat.arrays(), edges, nmax, *TREE)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_tree_c0_matches_oracle(fp, prec):
+    cat, edges, nmax = c0()
+    assert oracle.tree_levels(edges, *TREE) == [0, 0, 1, 2]
+    got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision=prec, tree=TREE)
+    err = rel_per_mu(got, c0_tree_ref())
+    print(prec, err)
+    assert np.all(err < 1e-5), err
+    # and it is an approximation: not the discrete result
+    exact = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision=prec)
+    assert np.max(rel_per_mu(got, exact)) > 1e-4
+
+
+def test_tree_raw_sums_match_oracle(fp):
+    cat, edges, nmax = c0()
+    got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp16", tree=TREE,
+                                      subtract_degenerate=False)
+    ref = oracle.upsilon_tree(*cat.arrays(), edges, nmax, *TREE, distinct=False)
+    assert np.all(rel_per_mu(got, ref) < 1e-5)
+
+
+def test_tree_tiles_match_single_tile(fp):
+    """Ragged tiles give the single-tile result.  The tree runs in the mixed
+    paths, whose contraction sums blocks of 512 centres in binary32 starting
+    at each tile's first centre, so tilings agree to that blocked binary32
+    accuracy (2^-24 sqrt(512) ~ 1e-6), not bit for bit; the same tiling
+    twice is bitwise equal."""
+    cat, edges, nmax = c0()
+    one = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp16", tree=TREE)
+    many = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp16", tree=TREE,
+                                       tile_centers=333)
+    again = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp16", tree=TREE,
+                                        tile_centers=333)
+    assert np.all(rel_per_mu(many, one) < 2e-6)
+    assert np.array_equal(many, again)
+
+
+def test_tree_fine_grid_is_discrete(fp):
+    """Cells far below the galaxy spacing hold one galaxy each: every bin on a
+    grid, same result as the discrete estimator."""
+    cat, edges, nmax = c0()
+    idx = np.random.default_rng(5).choice(cat.n, 400, replace=False)
+    c = synth.subset(cat, idx)
+    tree = (1e-4, 1, 2.0)
+    assert oracle.tree_levels(edges, *tree) == [1, 1, 1, 1]
+    got = fp.estimate_4pcf_multipoles(*c.arrays(), edges, nmax, precision="fp16", tree=tree)
+    exact = fp.estimate_4pcf_multipoles(*c.arrays(), edges, nmax, precision="fp16")
+    assert np.all(rel_per_mu(got, exact) < 1e-5)
+
+
+def test_tree_without_qualifying_bins_is_exact(fp):
+    cat, edges, nmax = c0()
+    got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp16", tree=(0.5, 3, 1e6))
+    exact = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp16")
+    assert np.array_equal(got, exact)
+
+
+def test_tree_fp64_unsupported(fp):
+    cat, edges, nmax = c0()
+    with pytest.raises(fp.Fpcf4Error) as ei:
+        fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp64", tree=TREE)
+    assert ei.value.status == -2
+
+
+@functools.lru_cache(None)
+def grf1m():
+    cat, edges, nmax, _ = synth.workload("grf-1m")
+    return cat, edges, nmax
+
+
+def test_tree_grf1m_sampled_centres(fp):
+    """The 1e6-galaxy GRF catalogue with the paper's setting (0.5', 1', 2'
+    grids, r_min 40): seeded centres against the oracle."""
+    cat, edges, nmax = grf1m()
+    tree = (0.5, 3, 40.0)
+    lv = oracle.tree_levels(edges, *tree)
+    assert lv == [0] * 8 + [1, 1, 2, 2]
+    idx = np.random.default_rng(13).choice(cat.n, 6, replace=False)
+    got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp16", tree=tree, centers=idx)
+    ref = oracle.upsilon_tree(*cat.arrays(), edges, nmax, *tree, centers=idx)
+    err = rel_per_mu(got, ref)
+    print(err)
+    assert np.all(err < 1e-5), err
