@@ -211,6 +211,40 @@ def stage_b_roofline(ncent, nb, nmax, precision, ms):
             "frac_useful": useful / t / peak, "stage_ms": ms}
 
 
+TREE = (0.5, 3, 40.0)   # grids of 0.5', 1', 2' and r_min = 40 (the paper's setting)
+
+
+def tree_report(fp, dev, n, edges, nmax, precision, exact_out, exact_dt):
+    """The same estimate with the tree approximation: time per step and the
+    deviation from the discrete result per correlator."""
+    import torch
+
+    def run():
+        return fp.estimate_4pcf_multipoles(*dev, edges, nmax, precision=precision, tree=TREE)
+
+    run()
+    torch.cuda.synchronize()
+    fp.profile_enable(True)
+    t = time.perf_counter()
+    for _ in range(2):
+        res = run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / 2
+    prof = fp.profile_read()
+    fp.profile_enable(False)
+    a, b = res.cpu().numpy(), exact_out.cpu().numpy()
+    dev_mu = [float(np.linalg.norm(a[m] - b[m]) / np.linalg.norm(b[m])) for m in range(9)]
+    c = nmax
+    lo = (Ellipsis, slice(c - 2, c + 3), slice(c - 2, c + 3))   # |n2|, |n3| <= 2
+    dev_lo = [float(np.linalg.norm(a[m][lo] - b[m][lo]) / np.linalg.norm(b[m][lo])) for m in range(9)]
+    log(f"tree: {dt:.3f} s/step")
+    return {"delta1": TREE[0], "levels": TREE[1], "rmin": TREE[2], "value": n / dt, "unit": "centres/s",
+            "ms_per_step": dt * 1e3, "speedup_vs_discrete": exact_dt / dt,
+            "stage_a_ms_per_step": prof["stage_a_ms"] / 2,
+            "deviation_from_discrete_per_mu": dev_mu,
+            "deviation_from_discrete_per_mu_n_le_2": dev_lo}
+
+
 NATURAL_NPHI = 129   # angular bins per axis of the natural components (the paper's choice)
 
 
@@ -292,6 +326,7 @@ def main():
     ap.add_argument("--serve-lambda", type=float, default=SERVE_LAMBDA or 0.0,
                     help="arrival rate (requests/s); 0 = 0.7 / mean alone service time")
     ap.add_argument("--no-3pcf", action="store_true", help="skip the 3PCF run on the same catalogue")
+    ap.add_argument("--no-tree", action="store_true", help="skip the tree-approximation run")
     ap.add_argument("--no-natural", action="store_true",
                     help="skip the blockwise natural-component conversion of the result")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -394,6 +429,8 @@ def main():
                               [float(np.linalg.norm(c[m] - b[m]) / np.linalg.norm(b[m])) for m in range(9)]})
             log(f"bf16: {dtb:.3f} s/step")
         del ref
+    if not args.no_tree and args.precision != "fp64":
+        extra["tree"] = tree_report(fp, dev, cat.n, edges, nmax, args.precision, out, dt)
     if not args.no_natural:
         extra["natural_blocks"] = natural_report(fp, out, NATURAL_NPHI)
     if not args.no_3pcf:
