@@ -101,7 +101,17 @@ def cpu_baseline(cat, edges, nmax, seconds_target=15.0):
     t = time.perf_counter()
     oracle.upsilon_parallel(*cat.arrays(), edges, nmax, centers=idx, processes=procs)
     wall = time.perf_counter() - t
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": nsample / wall, "unit": "centres/s", "cores": procs, "kind": "oracle",
+            "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": f"{nsample} seeded centres of the same catalogue (all 1e6 galaxies as neighbours), "
                       f"FP64 NumPy oracle in {procs} processes, {wall:.1f} s wall"}
 
@@ -415,6 +425,9 @@ def main():
         extra.update({"fp64_value": cat.n / dt64, "fp64_ms_per_step": dt64 * 1e3,
                       "fp64_stage_ms_per_step": {k: p64[k + "_ms"] for k in ("stage_a", "relayout", "stage_b", "corr")},
                       "mixed_vs_fp64_rel_err_per_mu": err,
+                      # largest element error per mu, relative to that mu's largest |value|
+                      "mixed_vs_fp64_max_abs_err_per_mu": [float(np.abs(a[m] - b[m]).max() / np.abs(b[m]).max())
+                                                           for m in range(9)],
                       "mixed_speedup_vs_fp64": dt64 / dt})
         if not args.no_bf16 and args.precision != "bf16":
             run("bf16")

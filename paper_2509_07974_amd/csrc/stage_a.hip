@@ -343,6 +343,14 @@ template <typename T> struct Nb {
 // binary32 passes take their first power z^K0 from the ring (formed once per
 // neighbour by the lane that binned it); binary64 rings would not fit LDS
 template <typename T> constexpr bool kRingStarts = sizeof(T) == 4;
+// Exact binary32 ring: the weight w travels in the third component of the
+// start slots, so that every ring array a pass reads has the 16-byte stride
+// of q0 and one address serves all reads of a neighbour.  The reduced-
+// catalogue kernel keeps separate 8-byte starts and w (its ring also holds
+// the triple-block weights, and the larger slots would cost occupancy).
+template <typename T, bool RED> constexpr bool kPackW = sizeof(T) == 4 && !RED;
+template <typename T, bool PACK> struct QKsel { using type = Q2<T>; };
+template <typename T> struct QKsel<T, true> { using type = Q4<T>; };
 
 // Add one neighbour to the units of one pass.  Lanes with valid == false
 // add nothing.
@@ -424,10 +432,14 @@ template <typename T, int W, int NMX, bool RED> struct Shared {
   static constexpr int CAP = ring_cap(W);
   // ring of in-bin neighbours (z, a, b | c, d, e, v | w); the entries of a
   // round are appended in wave order, so a batch is 64 consecutive slots
+  static constexpr bool PACK = kPackW<T, RED>;
+  using QK = typename QKsel<T, PACK>::type;
+  static constexpr int NQK = kRingStarts<T> && W > 1 ? W - 1 : 1;
+  static constexpr bool HASQK = (kRingStarts<T> && W > 1) || PACK;
   Q4<T> q0[CAP];
   Q4<T> q1[CAP];
-  T qw[CAP];
-  Q2<T> qk[kRingStarts<T> && W > 1 ? W - 1 : 1][kRingStarts<T> && W > 1 ? CAP : 1];  // z^K0 of passes 1..W-1
+  QK qk[NQK][HASQK ? CAP : 1];  // z^K0 of passes 1..W-1 (and w, when PACK)
+  T qw[PACK ? 1 : CAP];
   Q4<T> q2[RED ? CAP : 1];  // pseudo-galaxies: (w g)^3, |w g|^2 w g cell sums
   T qu[RED ? CAP : 1];      // pseudo-galaxies: w^3 cell sum
   double stage[W][NMX * 64];  // per-wave epilogue staging of the binary64 sums
@@ -439,14 +451,15 @@ template <typename T, int W, int NMX, bool RED> struct Shared {
 // First powers z^K0 of passes P..W-1, each the previous one times
 // z^(K0[P] - K0[P-1]), written to the ring slot of the neighbour.
 template <typename T, int N, int P, typename SH>
-__device__ __forceinline__ void put_starts(SH& sh, unsigned slot, T zr, T zi, T pr, T pi) {
+__device__ __forceinline__ void put_starts(SH& sh, unsigned slot, T zr, T zi, T pr, T pi, T w) {
   if constexpr (P < Conf<T, N>::W) {
     constexpr int D = Conf<T, N>::PP.k0[P] - Conf<T, N>::PP.k0[P - 1];
     T dr, di;
     cpow<T, D>(zr, zi, dr, di);
     const T nr = pr * dr - pi * di, ni = pr * di + pi * dr;
-    sh.qk[P - 1][slot] = Q2<T>{nr, ni};
-    put_starts<T, N, P + 1>(sh, slot, zr, zi, nr, ni);
+    if constexpr (SH::PACK) sh.qk[P - 1][slot] = Q4<T>{nr, ni, w, T(0)};
+    else sh.qk[P - 1][slot] = Q2<T>{nr, ni};
+    put_starts<T, N, P + 1>(sh, slot, zr, zi, nr, ni, w);
   }
 }
 
@@ -488,13 +501,19 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
   auto fetch = [&](unsigned slot) -> Nb<T> {
     const Q4<T> u = sh.q0[slot];
     const Q4<T> v = sh.q1[slot];
-    T sr = T(0), si = T(0);
+    T sr = T(0), si = T(0), ww;
+    constexpr bool PK = kPackW<T, RED>;
     if constexpr (PASS > 0 && kRingStarts<T>) {
-      const Q2<T> k = sh.qk[PASS - 1][slot];
+      const auto k = sh.qk[PASS - 1][slot];
       sr = k.x;
       si = k.y;
+      if constexpr (PK) ww = k.z;
+      else ww = sh.qw[slot];
+    } else {
+      if constexpr (PK) ww = sh.qk[0][slot].z;
+      else ww = sh.qw[slot];
     }
-    Nb<T> q{u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w, sh.qw[slot], sr, si};
+    Nb<T> q{u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w, ww, sr, si};
     if constexpr (RED && PASS == 0) {
       const Q4<T> t = sh.q2[slot];
       q.p3 = t.x;
@@ -709,16 +728,20 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
               sh.q2[slot] = Q4<T>{gc.p3, gc.q3, gc.ea, gc.eb};
               sh.qu[slot] = gc.u;
             }
-            if constexpr (kRingStarts<T> && W > 1) put_starts<T, N, 1>(sh, slot, zr, zi, T(1), T(0));
+            if constexpr (kRingStarts<T> && W > 1) put_starts<T, N, 1>(sh, slot, zr, zi, T(1), T(0), vw);
+            else if constexpr (kPackW<T, RED>) sh.qk[0][slot] = Q4<T>{T(0), T(0), vw, T(0)};
             if constexpr (!RED) sh.q1[slot] = Q4<T>{va * va - vb * vb, T(2) * va * vb, va * va + vb * vb, vw * vw};
-            sh.qw[slot] = vw;
+            if constexpr (!kPackW<T, RED>) sh.qw[slot] = vw;
           }
           head += (unsigned)added;
           cnt += added;
           __syncthreads();
           // ---- every pass adds the complete batches
           while (head - tail >= 64u) {
-            add_pair<T, N, K0, K1, P0, NUO, RED>(acc, true, fetch((tail + lane) & (CAP - 1)));
+            // batches start on multiples of 64 (the ring is realigned at the
+            // end of every bin), so a batch never wraps around the ring
+            __builtin_assume((tail & 63u) == 0u);
+            add_pair<T, N, K0, K1, P0, NUO, RED>(acc, true, fetch((tail & (CAP - 1)) + lane));
             tail += 64u;
             if (++nblk == FOLD) {
               fold_all<T, NU, NM>(acc, mst, lane);
@@ -732,10 +755,13 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
       if (head != tail) {
         const bool valid = lane < head - tail;
         Nb<T> q{};
-        if (valid) q = fetch((tail + lane) & (CAP - 1));
+        __builtin_assume((tail & 63u) == 0u);
+        if (valid) q = fetch((tail & (CAP - 1)) + lane);
         add_pair<T, N, K0, K1, P0, NUO, RED>(acc, valid, q);
-        tail = head;
       }
+      // realign the ring: the next bin's first batch starts on a multiple of 64
+      head = (head + 63u) & ~63u;
+      tail = head;
       fold_all<T, NU, NM>(acc, mst, lane);
 
       // ---- epilogue: masters -> LDS -> record blocks of this pass
