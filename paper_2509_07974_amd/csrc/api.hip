@@ -69,7 +69,7 @@ struct PlanInfo {
   size_t sort_tmp = 0;
   // persistent buffers
   size_t o_gal, o_cells, o_centres, o_e2, o_edges, o_counters, o_bbox, o_bad,
-      o_pairs, o_part, o_ups, o_bpart, o_corr, o_cpart, o_acc3, o_part3, o_xg, o_xw, o_counts,
+      o_pairs, o_part, o_ups, o_bpart, o_yprep, o_corr, o_cpart, o_acc3, o_part3, o_xg, o_xw, o_counts,
       o_aos, o_region;
   int bslices = 1;             // centre slices of the contraction (partials when > 1)
   // tree approximation
@@ -178,6 +178,7 @@ fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   P.o_ups = take(P.ups_bytes);
   P.bslices = order == 4 ? contract_slices((int)std::min<int64_t>(P.tile, INT32_MAX), P.nmax) : 1;
   P.o_bpart = take(P.bslices > 1 ? P.ups_bytes * P.bslices : 0);
+  P.o_yprep = take(order == 4 && P.precision != FPCF4_FP64 ? yprep_bytes(P.nb, P.nmax, P.tile) : 0);
   P.o_corr = take(P.corr_bytes);
   P.o_cpart = take(P.corr_bytes * CORR_SLICES);
   P.o_acc3 = take(P.acc3_bytes);
@@ -433,6 +434,7 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
     b.ups = R->at<double>(P.o_ups);
     b.corr = R->at<double>(P.o_corr);
     b.part = P.bslices > 1 ? R->at<double>(P.o_bpart) : nullptr;
+    b.yprep = P.precision != FPCF4_FP64 ? R->at<double>(P.o_yprep) : nullptr;
     HIPCHK(launch_contract(b, P.precision, (int)P.ldc, a.xg, a.xw, a.maxima, s));
     if (prof) HIPCHK(hipEventRecord(evs[3], s));
     CorrArgs ca{a.rec, a.xg, a.xw, ncent, P.nb, P.nmax, (int32_t)P.ldc, b.corr,

@@ -153,10 +153,14 @@ struct StageBArgs {
   double* ups;              // [9][nb][nb][nb][nn][nn] complex128 accumulator
   double* corr;             // correction sums (see stage_b.hip)
   double* part;             // [contract_slices][9 nb^3 nn^2] complex partials, or null (one slice)
+  void* yprep;              // mixed paths: split Y operand of one group (yprep_bytes), reused per group
 };
+// bytes of the split Y operand buffer of the mixed contraction for a tile of ncent centres
+size_t yprep_bytes(int nb, int nmax, int64_t ncent);
 
 // Centre slices of the contraction: enough workgroups (one per (n2, n3) and
-// slice) to fill the chip, at least 2048 centres per slice, at most 8.
+// slice) to fill the chip (about 8192), at least 8192 centres per slice, at
+// most 32.
 __host__ __device__ inline int contract_slices(int ncent, int nmax) {
   const int nn2 = (2 * nmax + 1) * (2 * nmax + 1);
   int s = (8192 + nn2 - 1) / nn2;

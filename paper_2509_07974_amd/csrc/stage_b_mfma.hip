@@ -29,6 +29,11 @@
 // split Y operand) and take disjoint (b1, b3) column tiles.  The global loads
 // of chunk k+1 are issued into registers before the MFMAs of chunk k and
 // committed to the other LDS buffer after them.
+//
+// The split Y operand depends on (n2, centre) only, so in the mixed paths it
+// is formed once per group by yprep_kernel (conjugated, scaled, split into
+// hi/lo and laid out in MFMA lane order for every 32-centre chunk) instead
+// of once per (n2, n3) workgroup; the contraction copies it into LDS.
 #include "factors.hpp"
 #include "fpcf4_internal.hpp"
 
@@ -168,7 +173,25 @@ struct BArgs {
   const void* xg;          // per tile centre: complex (w g) in record precision
   const void* xw;          // per tile centre: w
   const unsigned* maxima;  // scaling maxima (mixed only)
+  void* yprep;             // mixed only: split Y operand of the group (yprep_kernel)
 };
+
+typedef unsigned u4 __attribute__((ext_vector_type(4)));   // 16 bytes: one H8
+
+// Mixed paths: the split Y operand of one correlator group, for every n2 and
+// every 32-centre chunk of the tile, in the order the contraction stages it:
+// [n2 + nmax][chunk][K-step][row tile][hi, lo][lane] of 8 16-bit values.
+// Entry (ks, m, lane) holds row r = 16 m + lane % 16 of (mu, re/im, b2) and
+// centres 16 ks + 4 (lane / 16) + (0..3) of the chunk, as
+// [ y_r, -y_i ] (real-output rows) or [ y_i, y_r ] (imaginary-output rows)
+// per centre, y = B^mu(b2, n2) (conjugated where the factor table says so)
+// times the power-of-two scale of b2; rows past the used ones and centres
+// past the tile are zero.
+__host__ __device__ constexpr int yprep_slots(int nmu, int nbc) { return (KC / 16) * mt_of(nmu, nbc) * 64; }
+inline size_t yprep_bytes_for(int nbc, int nmax, int64_t ncent) {
+  const int64_t nchunk = (ncent + KC - 1) / KC;
+  return (size_t)(2 * nmax + 1) * (size_t)nchunk * yprep_slots(2, nbc) * 2 * 16;
+}
 
 // Values a thread stages for one chunk: X and Z for two (bin, centre) slots
 // and the Y column of up to two (row tile, lane) slots, held in registers
@@ -178,6 +201,65 @@ struct Prefetch {
   C2<T> xc[NXS], av[NXS], cv[NXS];
   C2<T> y[NYS][4];
 };
+template <typename T, int NXS, int NYS>
+struct PrefetchP {          // mixed paths: Y comes split from yprep_kernel
+  C2<T> xc[NXS], av[NXS], cv[NXS];
+  u4 yh[NYS], yl[NYS];
+};
+
+template <int PREC, int G, int NBC>
+__global__ __launch_bounds__(256) void yprep_kernel(BArgs a) {
+  typedef typename Half8<PREC>::type H8;
+  constexpr Group GR = group_of(G);
+  constexpr MuFactors F0 = mu_factors(GR.mu[0]);
+  constexpr MuFactors F1 = mu_factors(GR.mu[1]);
+  constexpr int MT = mt_of(GR.nmu, NBC);
+  constexpr int NQ = yprep_slots(GR.nmu, NBC);
+  constexpr int NQX = yprep_slots(2, NBC);        // slot stride of the buffer (largest group)
+  const int nb = a.s.nb, n = a.s.nmax, nn = 2 * n + 1;
+  const int ncent = a.s.ncent;
+  const int64_t nchunk = (ncent + KC - 1) / KC;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nn * nchunk * NQ) return;
+  const int q = (int)(t % NQ);
+  const int64_t r1 = t / NQ;
+  const int64_t ch = r1 % nchunk;
+  const int n2i = (int)(r1 / nchunk);
+  const int n2 = n2i - n;
+  const Layout L = make_layout(n);
+  const int rowB0 = fac_entry_k(L, F0.B, F0.B.a * n2 + F0.B.c);
+  const int rowB1 = fac_entry_k(L, F1.B, F1.B.a * n2 + F1.B.c);
+  constexpr int famB = F0.B.fam == F_G ? 0 : 16;
+  const int ks = q / (MT * 64), m = (q / 64) % MT, l = q & 63;
+  const int r = 16 * m + (l & 15);
+  const int mrows = GR.nmu * 2 * nb;
+  float v[8];
+  if (r < mrows) {
+    const int mi = r / (2 * nb), part = (r % (2 * nb)) / nb, b2 = r % nb;
+    const int row = (mi ? rowB1 : rowB0) * nb + b2;
+    const bool cj = mi ? F1.B.conj : F0.B.conj;
+    const float sy = pow2_below(__uint_as_float(a.maxima[famB + b2]), 14);
+    const float* rec = reinterpret_cast<const float*>(a.s.rec);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t c = ch * KC + 16 * ks + 4 * (l >> 4) + u;
+      C2<float> y{0.f, 0.f};
+      if (c < ncent) y = ldrec(rec, (int64_t)row, a.ldc, (int)c);
+      if (cj) y.i = -y.i;
+      v[2 * u] = (part ? y.i : y.r) * sy;
+      v[2 * u + 1] = (part ? y.r : -y.i) * sy;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = 0.f;
+  }
+  H8 hi, lo;
+  split8v<PREC>(v, hi, lo);
+  u4* out = reinterpret_cast<u4*>(a.yprep) + ((int64_t)n2i * nchunk + ch) * NQX * 2;
+  const int e = (ks * MT + m) * 2 * 64 + l;
+  out[e] = __builtin_bit_cast(u4, hi);
+  out[e + 64] = __builtin_bit_cast(u4, lo);
+}
 
 // ---------------------------------------------------------------------------
 // mixed precision
@@ -218,8 +300,6 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
 
   const int rowA = fac_entry_k(L, F0.A, F0.A.a * n2 + F0.A.b * n3 + F0.A.c);
   const int rowC = fac_entry_k(L, F0.C, F0.C.b * n3 + F0.C.c);
-  const int rowB0 = fac_entry_k(L, F0.B, F0.B.a * n2 + F0.B.c);
-  const int rowB1 = fac_entry_k(L, F1.B, F1.B.a * n2 + F1.B.c);
   constexpr int famA = F0.A.fam == F_G ? 0 : 16;
   constexpr int famB = F0.B.fam == F_G ? 0 : 16;
   constexpr int famC = F0.C.fam == F_G ? 0 : 16;
@@ -249,25 +329,20 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
   // ---- staging: global -> registers (issue), registers -> LDS (commit)
   const C2<float>* xg = reinterpret_cast<const C2<float>*>(a.xg) + cbase;
   const float* xw = reinterpret_cast<const float*>(a.xw) + cbase;
-  Prefetch<float, NXS, NYS> pf;
-  // this thread's Y slots (K-step, row tile, lane) and their row meaning
-  int y_ks[NYS], y_m[NYS], y_l[NYS], y_part[NYS], y_b2[NYS], y_row[NYS], y_cj[NYS];
-  bool y_ok[NYS], y_on[NYS];
+  PrefetchP<float, NXS, NYS> pf;
+  // this thread's Y slots (K-step, row tile, lane): 16-byte copies from the
+  // split operand of this n2 (yprep_kernel)
+  constexpr int NQX = yprep_slots(2, NBC);
+  const int64_t ychunks = (a.s.ncent + KC - 1) / KC;
+  const u4* yp = reinterpret_cast<const u4*>(a.yprep) + (int64_t)(n2 + n) * ychunks * NQX * 2;
+  int y_off[NYS];
+  bool y_on[NYS];
 #pragma unroll
   for (int h = 0; h < NYS; ++h) {
     const int q = tid + NT * h;
-    y_ks[h] = q / (MT * 64);
-    y_m[h] = (q / 64) % MT;
-    y_l[h] = q & 63;
-    y_on[h] = y_ks[h] < KS;
-    const int r = 16 * y_m[h] + (y_l[h] & 15);
-    y_ok[h] = y_on[h] && r < mrows;
-    const int rr = y_ok[h] ? r : 0;
-    const int mi = rr / (2 * nb);
-    y_part[h] = (rr % (2 * nb)) / nb;
-    y_b2[h] = rr % nb;
-    y_row[h] = (mi ? rowB1 : rowB0) * nb + y_b2[h];
-    y_cj[h] = mi ? F1.B.conj : F0.B.conj;
+    const int ks = q / (MT * 64), m = (q / 64) % MT, l = q & 63;
+    y_on[h] = ks < KS;
+    y_off[h] = y_on[h] ? (ks * MT + m) * 2 * 64 + l : 0;
   }
   // Loads are unconditional (bin and centre clamped into the tile) so that
   // they stay in flight across the MFMAs; commit masks what lies outside.
@@ -282,13 +357,11 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
       pf.av[h] = ldrec(rec, (int64_t)rowA * nb + bl, ldc, cl);
       pf.cv[h] = ldrec(rec, (int64_t)rowC * nb + bl, ldc, cl);
     }
+    const u4* yc = yp + ((int64_t)(cbase + c0) / KC) * NQX * 2;
 #pragma unroll
     for (int h = 0; h < NYS; ++h) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int c = c0 + 16 * y_ks[h] + 4 * (y_l[h] >> 4) + u;
-        pf.y[h][u] = ldrec(rec, (int64_t)y_row[h], ldc, c < ncent ? c : ncent - 1);
-      }
+      pf.yh[h] = yc[y_off[h]];
+      pf.yl[h] = yc[y_off[h] + 64];
     }
   };
   auto commit = [&](int c0, int buf) {
@@ -303,34 +376,20 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
         if (F0.C.conj) cv.i = -cv.i;
         const bool live = c0 + cc < ncent;
         const float sx = live ? sc_lds[0][b] : 0.f, sz = live ? sc_lds[2][b] : 0.f;
-        Xs[buf][b][cc] = {(xc.r * av.r - xc.i * av.i) * sx, (xc.r * av.i + xc.i * av.r) * sx};
+        // explicit fused forms: the rounding does not depend on how the
+        // compiler would contract the expression
+        Xs[buf][b][cc] = {__builtin_fmaf(xc.r, av.r, -(xc.i * av.i)) * sx,
+                          __builtin_fmaf(xc.r, av.i, xc.i * av.r) * sx};
         Zs[buf][b][cc] = {cv.r * sz, cv.i * sz};
       }
     }
+    // the split Y operand, copied as prepared (slots in the order of Ys)
+    H8* ys = &Ys[buf][0][0][0][0];
 #pragma unroll
     for (int h = 0; h < NYS; ++h) {
       if (!y_on[h]) continue;
-      float v[8];
-      if (y_ok[h]) {
-        const int part = y_part[h];
-        const float sy = sc_lds[1][y_b2[h]];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          C2<float> y = pf.y[h][u];
-          if (y_cj[h]) y.i = -y.i;
-          if (c0 + 16 * y_ks[h] + 4 * (y_l[h] >> 4) + u >= ncent) y = {0.f, 0.f};
-          // row part 0 (real out): [ y_r, -y_i ];  part 1 (imag out): [ y_i, y_r ]
-          v[2 * u] = (part ? y.i : y.r) * sy;
-          v[2 * u + 1] = (part ? y.r : -y.i) * sy;
-        }
-      } else {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = 0.f;
-      }
-      H8 hi, lo;
-      split8v<PREC>(v, hi, lo);
-      Ys[buf][y_ks[h]][y_m[h]][0][y_l[h]] = hi;
-      Ys[buf][y_ks[h]][y_m[h]][1][y_l[h]] = lo;
+      ys[y_off[h]] = __builtin_bit_cast(H8, pf.yh[h]);
+      ys[y_off[h] + 64] = __builtin_bit_cast(H8, pf.yl[h]);
     }
   };
 
@@ -394,8 +453,8 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
         for (int u = 0; u < 4; ++u) {
           const C2<float> xv = Xs[buf][b1c[t]][cb + u];
           const C2<float> zv = Zs[buf][b3c[t]][cb + u];
-          v[2 * u] = xv.r * zv.r - xv.i * zv.i;
-          v[2 * u + 1] = xv.r * zv.i + xv.i * zv.r;
+          v[2 * u] = __builtin_fmaf(xv.r, zv.r, -(xv.i * zv.i));
+          v[2 * u + 1] = __builtin_fmaf(xv.r, zv.i, xv.i * zv.r);
         }
         H8 rh, rl;
         split8v<PREC>(v, rh, rl);
@@ -621,12 +680,21 @@ template <int G, int NBC>
 static void launch_group_nbc(const BArgs& a, int precision, int nsl, hipStream_t s) {
   const int nn = 2 * a.s.nmax + 1;
   const dim3 grid(nn * nn, nsl), block(64 * wb_of(NBC));
-  if (precision == FPCF4_FP64)
+  if (precision == FPCF4_FP64) {
     hipLaunchKernelGGL((contract_f64_kernel<G, NBC>), grid, block, 0, s, a);
-  else if (precision == FPCF4_MIXED_FP16)
+    return;
+  }
+  // the group's split Y operand, then the contraction that copies it
+  const int64_t nchunk = (a.s.ncent + KC - 1) / KC;
+  const int64_t nthreads = (int64_t)nn * nchunk * yprep_slots(group_of(G).nmu, NBC);
+  const dim3 pgrid((unsigned)((nthreads + 255) / 256));
+  if (precision == FPCF4_MIXED_FP16) {
+    hipLaunchKernelGGL((yprep_kernel<FPCF4_MIXED_FP16, G, NBC>), pgrid, dim3(256), 0, s, a);
     hipLaunchKernelGGL((contract_mixed_kernel<FPCF4_MIXED_FP16, G, NBC>), grid, block, 0, s, a);
-  else
+  } else {
+    hipLaunchKernelGGL((yprep_kernel<FPCF4_MIXED_BF16, G, NBC>), pgrid, dim3(256), 0, s, a);
     hipLaunchKernelGGL((contract_mixed_kernel<FPCF4_MIXED_BF16, G, NBC>), grid, block, 0, s, a);
+  }
 }
 
 template <int G>
@@ -646,10 +714,16 @@ __global__ void contract_reduce_kernel(const double* part, int nsl, int64_t n2, 
   ups[i] += v;
 }
 
+size_t yprep_bytes(int nb, int nmax, int64_t ncent) {
+  const int nbc = nb <= 8 ? 8 : (nb <= 12 ? 12 : 16);
+  return yprep_bytes_for(nbc, nmax, ncent);
+}
+
 hipError_t launch_contract(const StageBArgs& sb, int precision, int ldc, const void* xg,
                            const void* xw, const unsigned* maxima, hipStream_t s) {
   if (sb.ncent <= 0) return hipSuccess;
-  BArgs a{sb, ldc, xg, xw, maxima};
+  if (precision != FPCF4_FP64 && sb.yprep == nullptr) return hipErrorInvalidValue;
+  BArgs a{sb, ldc, xg, xw, maxima, sb.yprep};
   const int nsl = sb.part ? contract_slices(sb.ncent, sb.nmax) : 1;
   hipError_t e;
   if ((e = launch_group<0>(a, precision, nsl, s)) != hipSuccess) return e;
