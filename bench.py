@@ -395,7 +395,9 @@ def main():
     achieved = pairs_per_launch * stage_a_flops_per_pair(nmax) / (a_ms * 1e-3)
     executed = pairs_per_launch * stage_a_flops_executed_per_pair(nmax) / (a_ms * 1e-3)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": stage_a_traffic(),
+            "frac": achieved / peak,
+            # the committed counters cover the binary32 kernel on grf-1m only
+            "traffic": stage_a_traffic() if args.workload == "grf-1m" and args.precision != "fp64" else None,
             "kernel": "stage_a_kernel (pair multipoles)",
             "avg_launch_ms": a_ms, "launches_per_step": launches / steps,
             "pairs_per_launch": pairs_per_launch,
