@@ -408,8 +408,8 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
     a.rcell[d - 1] = R->at<int32_t>(P.o_rcell[d - 1]);
   }
   int nlaunch = 0;
-  if (P.precision == FPCF4_FP64) HIPCHK(launch_stage_a<double>(P.nmax, a, s, &nlaunch, evs[1]));
-  else HIPCHK(launch_stage_a<float>(P.nmax, a, s, &nlaunch, evs[1]));
+  if (P.precision == FPCF4_FP64) HIPCHK(launch_stage_a<double>(P.nmax, P.order, a, s, &nlaunch, evs[1]));
+  else HIPCHK(launch_stage_a<float>(P.nmax, P.order, a, s, &nlaunch, evs[1]));
   if (prof) HIPCHK(hipEventRecord(evs[2], s));
   if (stage_b && P.order == 3) {
     ThreeArgs t3{a.rec, a.xg, a.xw, ncent, P.nb, P.nmax, P.m3, 2 * P.m3 + 1, (int32_t)P.ldc,

@@ -142,7 +142,7 @@ hipError_t reduced_build(const double* x, const double* y, const double* g1, con
 // of pair-kernel launches in *nlaunch; records `mid` (if not null) between
 // the two.
 template <typename T>
-hipError_t launch_stage_a(int nmax, const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t mid);
+hipError_t launch_stage_a(int nmax, int order, const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t mid);
 
 struct StageBArgs {
   const void* rec;          // records of the tile

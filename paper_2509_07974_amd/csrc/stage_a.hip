@@ -42,15 +42,34 @@ namespace fpcf4 {
 namespace sa {
 
 enum { FA = 0, FB, FC, FD, FW, FE, FV, NF };
-constexpr int NSPECIAL = 15;  // P8, Q8, P4, Q4, EA4, EB4 (complex); EA0, EB0, U (real)
+
+// Order plan.  The plan index n is the record order nmax for the 4PCF; an
+// index 3PCF_PLAN + m selects the plan of the shear 3PCF on records of order
+// m: the same record layout, but only the orders the 3PCF reads are formed
+// (G up to 2m + 3, W up to 2m, and of the same-neighbour families Q up to 6,
+// A up to 2, V at 0: the blocks Q_-6, Q_-2, A_2, V_0 of its corrections),
+// and no triple-counting blocks.
+constexpr int PLAN3 = 100;
+__host__ __device__ constexpr bool is3(int n) { return n >= PLAN3; }
+__host__ __device__ constexpr int nord(int n) { return is3(n) ? n - PLAN3 : n; }
+// special units of pass 0: P8, Q8, P4, Q4, EA4, EB4 (complex); EA0, EB0, U (real)
+__host__ __device__ constexpr int nspecial(int n) { return is3(n) ? 0 : 15; }
+constexpr int NSPECIAL = 15;
 
 __host__ __device__ constexpr int kmax_f(int n, int f) {
-  return (f == FA || f == FB) ? 2 * n + 3
-       : (f == FC || f == FD) ? imax(2 * n + 5, n + 6)
-       : (f == FE)            ? imax(2 * n + 1, n + 2)
-                              : 2 * n;
+  return is3(n) ? ((f == FA || f == FB) ? 2 * nord(n) + 3
+                 : (f == FC || f == FD) ? 6
+                 : (f == FE)            ? 2
+                 : (f == FW)            ? 2 * nord(n)
+                                        : 0)
+                : ((f == FA || f == FB) ? 2 * n + 3
+                 : (f == FC || f == FD) ? imax(2 * n + 5, n + 6)
+                 : (f == FE)            ? imax(2 * n + 1, n + 2)
+                                        : 2 * n);
 }
-__host__ __device__ constexpr int ktop(int n) { return imax(2 * n + 5, n + 6); }
+__host__ __device__ constexpr int ktop(int n) {
+  return is3(n) ? imax(2 * nord(n) + 3, 6) : imax(2 * n + 5, n + 6);
+}
 __host__ __device__ constexpr int units_at(int n, int k) {
   int u = 0;
   for (int f = 0; f < NF; ++f)
@@ -58,7 +77,7 @@ __host__ __device__ constexpr int units_at(int n, int k) {
   return u;
 }
 __host__ __device__ constexpr int total_units(int n) {
-  int u = NSPECIAL;
+  int u = nspecial(n);
   for (int k = 0; k <= ktop(n); ++k) u += units_at(n, k);
   return u;
 }
@@ -74,7 +93,7 @@ __host__ __device__ constexpr PassPlan greedy(int n, int cap) {
   PassPlan P{};
   int k = 0;
   while (k <= ktop(n) && P.np < 32) {
-    int used = (P.np == 0) ? NSPECIAL : 0;
+    int used = (P.np == 0) ? nspecial(n) : 0;
     const int start = k;
     while (k <= ktop(n) && (k == start || used + units_at(n, k) <= cap)) {
       used += units_at(n, k);
@@ -102,7 +121,7 @@ __host__ __device__ constexpr PassPlan plan_exact(int n, int w) {
     const int k0 = P.k0[big], k1 = P.k1[big];
     int best = k0, bestmax = 1 << 30;
     for (int split = k0; split < k1; ++split) {
-      int lo = (big == 0) ? NSPECIAL : 0, hi = 0;
+      int lo = (big == 0) ? nspecial(n) : 0, hi = 0;
       for (int k = k0; k <= split; ++k) lo += units_at(n, k);
       for (int k = split + 1; k <= k1; ++k) hi += units_at(n, k);
       const int m = imax(lo, hi);
@@ -113,7 +132,7 @@ __host__ __device__ constexpr PassPlan plan_exact(int n, int w) {
       P.k1[p] = P.k1[p - 1];
       P.units[p] = P.units[p - 1];
     }
-    int lo = (big == 0) ? NSPECIAL : 0, hi = 0;
+    int lo = (big == 0) ? nspecial(n) : 0, hi = 0;
     for (int k = k0; k <= best; ++k) lo += units_at(n, k);
     for (int k = best + 1; k <= k1; ++k) hi += units_at(n, k);
     P.k1[big] = best;
@@ -132,13 +151,16 @@ __host__ __device__ constexpr int max_units(const PassPlan& P) {
 }
 // Waves per workgroup (one per pass): a power of two, so that two or more
 // workgroups tile the four SIMDs of a CU evenly.  Binary32: the fewest waves
-// whose passes fit 132 accumulators, at least four from nmax 5 on; binary64
-// (two registers per accumulator): passes of at most 72.
+// whose passes fit 132 accumulators, at least four from nmax 5 on (4PCF
+// plan) or at least two (3PCF plan, measured best at record order 5: two
+// passes of 54 units ahead of one and four); binary64 (two registers per
+// accumulator): passes of at most 72.
 __host__ __device__ constexpr int choose_waves(int n, bool fp64) {
   const int lim = fp64 ? 72 : 132;
   int w = 1;
   while (w < 8 && max_units(plan_exact(n, w)) > lim) w *= 2;
-  if (!fp64 && n >= 5 && w < 4) w = 4;
+  if (!fp64 && !is3(n) && n >= 5 && w < 4) w = 4;
+  if (!fp64 && is3(n) && w < 2) w = 2;
   return w;
 }
 
@@ -374,7 +396,7 @@ __device__ __forceinline__ void add_pair(T* acc, bool valid, Nb<T> q) {
     cpow<T, K0>(zr, zi, pr, pi);
   }
   acc_orders<T, N, K0, K1, K0>(acc, val, pr, pi, T(0), T(0), zr, zi, T(2) * zr);
-  if constexpr (P0) {
+  if constexpr (P0 && !is3(N)) {
     // triple-counting blocks: T_-8, T_-4 (weight (w g)^3), M_-4, M_0
     // (weight |w g|^2 w g) and U (weight w^3)
     const T z2r = zr * zr - zi * zi, z2i = T(2) * zr * zi;
@@ -484,14 +506,15 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
   constexpr int K1 = Conf<T, N>::PP.k1[PASS];
   constexpr bool P0 = (PASS == 0);
   constexpr int NUO = ubase(N, K0, K1 + 1);          // order units
-  constexpr int NU = NUO + (P0 ? NSPECIAL : 0);
+  constexpr int NU = NUO + (P0 ? nspecial(N) : 0);
   constexpr int NM = (NU + 63) / 64;
   constexpr int FOLD = Budget<T>::fold;
   static_assert(NM <= Conf<T, N>::NMX, "staging block");
 
   const Gal<T>* __restrict__ gal = reinterpret_cast<const Gal<T>*>(a.cat.gal);
   const Grid g = a.cat.g;
-  const Layout L = make_layout(N);
+  constexpr int NO = nord(N);   // record order
+  const Layout L = make_layout(NO);
   const int nb = a.nb;
 
   const int xcd0 = blockIdx.x & 7;
@@ -778,10 +801,13 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
       for (int e = (int)lane; e < L.mpc; e += 64) {
         double re = 0.0, im = 0.0;
         bool mine = false;
+        // orders the plan does not form (3PCF plan) are written as zeros by pass 0
         if (e < L.offW) {                       // G_k
-          const int k = e - (2 * N + 3);
+          const int k = e - (2 * NO + 3);
           const int ko = k < 0 ? -k : k;
-          if (ko >= K0 && ko <= K1) {
+          if (ko > kmax_f(N, FA)) {
+            mine = P0;
+          } else if (ko >= K0 && ko <= K1) {
             mine = true;
             const double ar = su(FA, ko, 0), ai = su(FA, ko, 1);
             const double br = su(FB, ko, 0), bi = su(FB, ko, 1);
@@ -789,9 +815,11 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
             else        { re = ar + bi; im = br - ai; }
           }
         } else if (e < L.offQ) {                // W_k
-          const int k = e - L.offW - 2 * N;
+          const int k = e - L.offW - 2 * NO;
           const int ko = k < 0 ? -k : k;
-          if (ko >= K0 && ko <= K1) {
+          if (ko > kmax_f(N, FW)) {
+            mine = P0;
+          } else if (ko >= K0 && ko <= K1) {
             mine = true;
             re = su(FW, ko, 0);
             im = (k >= 0 ? 1.0 : -1.0) * su(FW, ko, 1);
@@ -799,7 +827,9 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
         } else if (e < L.offA) {                // Q_k
           const int k = e - L.offQ + L.qlo;
           const int ko = k < 0 ? -k : k;
-          if (ko >= K0 && ko <= K1) {
+          if (ko > kmax_f(N, FC)) {
+            mine = P0;
+          } else if (ko >= K0 && ko <= K1) {
             mine = true;
             const double cr = su(FC, ko, 0), ci = su(FC, ko, 1);
             const double dr = su(FD, ko, 0), di = su(FD, ko, 1);
@@ -808,10 +838,14 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
           }
         } else if (e < L.offV) {                // A_k, k >= 0
           const int k = e - L.offA;
-          if (k >= K0 && k <= K1) { mine = true; re = su(FE, k, 0); im = su(FE, k, 1); }
+          if (k > kmax_f(N, FE)) mine = P0;
+          else if (k >= K0 && k <= K1) { mine = true; re = su(FE, k, 0); im = su(FE, k, 1); }
         } else if (e < L.offS) {                // V_k, k >= 0
           const int k = e - L.offV;
-          if (k >= K0 && k <= K1) { mine = true; re = su(FV, k, 0); im = su(FV, k, 1); }
+          if (k > kmax_f(N, FV)) mine = P0;
+          else if (k >= K0 && k <= K1) { mine = true; re = su(FV, k, 0); im = su(FV, k, 1); }
+        } else if (P0 && is3(N)) {              // no triple-counting blocks in the 3PCF plan
+          mine = true;
         } else if (P0) {                        // T_-8, T_-4, M_-4, M_0, U
           const int sp = e - L.offS;
           mine = true;
@@ -963,18 +997,18 @@ hipError_t launch_n(const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t
   if (e != hipSuccess) return e;
   *nlaunch = 1;
   if (red) {
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 4 && !is3(N)) {
       StageAArgs ar = a;
       ar.bin_mask = red;
       ar.work_counter = a.work_counter + 8;
       if ((e = launch_pairs<T, N, true>(ar, s)) != hipSuccess) return e;
       *nlaunch = 2;
     } else {
-      return hipErrorInvalidValue;   // reduced catalogues are binary32 only
+      return hipErrorInvalidValue;   // reduced catalogues: binary32 4PCF only
     }
   }
   if (mid != nullptr && (e = hipEventRecord(mid, s)) != hipSuccess) return e;
-  const int mpc = make_layout(N).mpc;
+  const int mpc = make_layout(nord(N)).mpc;
   const dim3 grid((a.ncent + 63) / 64, a.nb, (mpc + 63) / 64);
   hipLaunchKernelGGL(transpose_kernel<T>, grid, dim3(256), 0, s, reinterpret_cast<const T*>(a.rec_aos),
                      reinterpret_cast<T*>(a.rec), a.ncent, a.nb, mpc, a.ldc);
@@ -988,11 +1022,15 @@ hipError_t launch_n(const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t
 // compiling in parallel.
 template hipError_t sa::launch_n<float, FPCF4_STAGE_A_N>(const StageAArgs&, hipStream_t, int*, hipEvent_t);
 template hipError_t sa::launch_n<double, FPCF4_STAGE_A_N>(const StageAArgs&, hipStream_t, int*, hipEvent_t);
+template hipError_t sa::launch_n<float, sa::PLAN3 + FPCF4_STAGE_A_N>(const StageAArgs&, hipStream_t, int*, hipEvent_t);
+template hipError_t sa::launch_n<double, sa::PLAN3 + FPCF4_STAGE_A_N>(const StageAArgs&, hipStream_t, int*, hipEvent_t);
 #else
 namespace sa {
 #define FPCF4_DECL_N(NN)                                                         \
   extern template hipError_t launch_n<float, NN>(const StageAArgs&, hipStream_t, int*, hipEvent_t); \
-  extern template hipError_t launch_n<double, NN>(const StageAArgs&, hipStream_t, int*, hipEvent_t);
+  extern template hipError_t launch_n<double, NN>(const StageAArgs&, hipStream_t, int*, hipEvent_t); \
+  extern template hipError_t launch_n<float, PLAN3 + NN>(const StageAArgs&, hipStream_t, int*, hipEvent_t); \
+  extern template hipError_t launch_n<double, PLAN3 + NN>(const StageAArgs&, hipStream_t, int*, hipEvent_t);
 FPCF4_DECL_N(0) FPCF4_DECL_N(1) FPCF4_DECL_N(2) FPCF4_DECL_N(3) FPCF4_DECL_N(4)
 FPCF4_DECL_N(5) FPCF4_DECL_N(6) FPCF4_DECL_N(7) FPCF4_DECL_N(8) FPCF4_DECL_N(9)
 FPCF4_DECL_N(10) FPCF4_DECL_N(11) FPCF4_DECL_N(12) FPCF4_DECL_N(13) FPCF4_DECL_N(14)
@@ -1001,9 +1039,10 @@ FPCF4_DECL_N(15) FPCF4_DECL_N(16)
 }  // namespace sa
 
 template <typename T>
-hipError_t launch_stage_a(int nmax, const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t mid) {
+hipError_t launch_stage_a(int nmax, int order, const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t mid) {
   switch (nmax) {
-#define FPCF4_CASE(NN) case NN: return sa::launch_n<T, NN>(a, s, nlaunch, mid);
+#define FPCF4_CASE(NN) \
+  case NN: return order == 3 ? sa::launch_n<T, sa::PLAN3 + NN>(a, s, nlaunch, mid) : sa::launch_n<T, NN>(a, s, nlaunch, mid);
     FPCF4_CASE(0) FPCF4_CASE(1) FPCF4_CASE(2) FPCF4_CASE(3) FPCF4_CASE(4)
     FPCF4_CASE(5) FPCF4_CASE(6) FPCF4_CASE(7) FPCF4_CASE(8) FPCF4_CASE(9)
     FPCF4_CASE(10) FPCF4_CASE(11) FPCF4_CASE(12) FPCF4_CASE(13) FPCF4_CASE(14)
@@ -1012,8 +1051,8 @@ hipError_t launch_stage_a(int nmax, const StageAArgs& a, hipStream_t s, int* nla
     default: return hipErrorInvalidValue;
   }
 }
-template hipError_t launch_stage_a<float>(int, const StageAArgs&, hipStream_t, int*, hipEvent_t);
-template hipError_t launch_stage_a<double>(int, const StageAArgs&, hipStream_t, int*, hipEvent_t);
+template hipError_t launch_stage_a<float>(int, int, const StageAArgs&, hipStream_t, int*, hipEvent_t);
+template hipError_t launch_stage_a<double>(int, int, const StageAArgs&, hipStream_t, int*, hipEvent_t);
 #endif
 
 }  // namespace fpcf4
