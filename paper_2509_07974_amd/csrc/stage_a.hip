@@ -54,7 +54,6 @@ __host__ __device__ constexpr bool is3(int n) { return n >= PLAN3; }
 __host__ __device__ constexpr int nord(int n) { return is3(n) ? n - PLAN3 : n; }
 // special units of pass 0: P8, Q8, P4, Q4, EA4, EB4 (complex); EA0, EB0, U (real)
 __host__ __device__ constexpr int nspecial(int n) { return is3(n) ? 0 : 15; }
-constexpr int NSPECIAL = 15;
 
 __host__ __device__ constexpr int kmax_f(int n, int f) {
   return is3(n) ? ((f == FA || f == FB) ? 2 * nord(n) + 3

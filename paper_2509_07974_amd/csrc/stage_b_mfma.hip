@@ -193,16 +193,11 @@ inline size_t yprep_bytes_for(int nbc, int nmax, int64_t ncent) {
   return (size_t)(2 * nmax + 1) * (size_t)nchunk * yprep_slots(2, nbc) * 2 * 16;
 }
 
-// Values a thread stages for one chunk: X and Z for two (bin, centre) slots
-// and the Y column of up to two (row tile, lane) slots, held in registers
-// across the compute of the previous chunk (software pipelining).
+// Values a thread stages for one chunk: X and Z for NXS (bin, centre) slots
+// and the split Y operand of NYS (K-step, row tile, lane) slots, held in
+// registers across the compute of the previous chunk (software pipelining).
 template <typename T, int NXS, int NYS>
-struct Prefetch {
-  C2<T> xc[NXS], av[NXS], cv[NXS];
-  C2<T> y[NYS][4];
-};
-template <typename T, int NXS, int NYS>
-struct PrefetchP {          // mixed paths: Y comes split from yprep_kernel
+struct PrefetchP {
   C2<T> xc[NXS], av[NXS], cv[NXS];
   u4 yh[NYS], yl[NYS];
 };
