@@ -176,7 +176,7 @@ __host__ __device__ constexpr int uidx(int n, int k0, int f, int k) {
 }
 
 template <typename T> struct Budget;
-template <> struct Budget<float> { static constexpr int fold = 64; };
+template <> struct Budget<float> { static constexpr int fold = 128; };
 template <> struct Budget<double> { static constexpr int fold = 1 << 30; };
 
 __device__ __forceinline__ double r2_exact(double dx, double dy) {
