@@ -281,6 +281,9 @@ fpcf4_status request_init(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   HIPCHK(hipMemsetAsync(R->ws + P.o_pairs, 0, 16, s));
   if (P.ups_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_ups, 0, P.ups_bytes, s));
   if (P.corr_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_corr, 0, P.corr_bytes, s));
+  // slice partials: the slots of correction sums shared with a smaller mu are
+  // never written, so they must hold zeros for the slice reduction
+  if (P.corr_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_cpart, 0, P.corr_bytes * CORR_SLICES, s));
   if (P.acc3_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_acc3, 0, P.acc3_bytes, s));
   std::vector<double> e2(P.nb + 1);
   for (int b = 0; b <= P.nb; ++b) e2[b] = bins->edges[b] * bins->edges[b];

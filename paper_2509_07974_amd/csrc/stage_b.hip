@@ -50,6 +50,9 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   else if ((r -= nn) < nn) { kind = 1; ord = r - n; }
   else if ((r -= nn) < ns) { kind = 2; ord = r - 2 * n; }
   else { kind = 3; }
+  // a sum shared with a smaller mu is formed there only (the finalisation
+  // reads it from that mu); this workgroup has nothing to do
+  if (corr_canon(mu, kind) != mu) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const MuFactors F = mu_factors(mu);
   const MuCorr C = mu_corr(mu);
@@ -256,20 +259,26 @@ __global__ void finalize_kernel(const double* raw, const double* corr, int nb, i
       const int b2 = (int)(t % nb); t /= nb;
       const int b1 = (int)(t % nb); t /= nb;
       const int mu = (int)t;
-      const double* C = corr + 2 * (int64_t)mu * corr_mu_elems(nb, n);
+      constexpr CorrCanon canon = corr_canon_table();
+      // each kind's sum lives at the smallest mu that shares it
+      auto Ck = [&](int kind) { return corr + 2 * (int64_t)canon.c[mu][kind] * corr_mu_elems(nb, n); };
       if (b1 == b2) {
+        const double* C = Ck(0);
         const int64_t q = ((int64_t)b1 * nb + b3) * nn + (n3 + n);
         re -= C[2 * q]; im -= C[2 * q + 1];
       }
       if (b1 == b3) {
+        const double* C = Ck(1);
         const int64_t q = (int64_t)nb * nb * nn + ((int64_t)b1 * nb + b2) * nn + (n2 + n);
         re -= C[2 * q]; im -= C[2 * q + 1];
       }
       if (b2 == b3) {
+        const double* C = Ck(2);
         const int64_t q = 2LL * nb * nb * nn + ((int64_t)b1 * nb + b2) * ns + (n2 + n3 + 2 * n);
         re -= C[2 * q]; im -= C[2 * q + 1];
       }
       if (b1 == b2 && b2 == b3) {
+        const double* C = Ck(3);
         const int64_t q = 2LL * nb * nb * nn + (int64_t)nb * nb * ns + b1;
         re += 2.0 * C[2 * q]; im += 2.0 * C[2 * q + 1];
       }
