@@ -93,6 +93,27 @@ def test_centre_subset(fp):
 
 
 @functools.lru_cache(None)
+def orders_case(nmax):
+    cat = synth.uniform_catalogue(70 + nmax, 300, 30.0)
+    edges = synth.log_edges(1.0, 15.0, 3)
+    return cat, edges, oracle.upsilon(*cat.arrays(), edges, nmax)
+
+
+@pytest.mark.parametrize("nmax", [0, 1, 5, 16])
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_multipole_orders(fp, nmax, prec):
+    """The smallest and largest supported nmax and one in between: each is
+    its own stage (a) kernel with its own split of the orders into passes
+    (one pass at nmax 0 and 1, four at 5 and 16 in binary32; up to eight in
+    binary64) and its own contraction tile counts."""
+    cat, edges, ref = orders_case(nmax)
+    got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision=prec)
+    assert got.shape == ref.shape
+    err = rel_per_mu(got, ref)
+    assert np.all(err < TOL[prec]), (nmax, prec, err)
+
+
+@functools.lru_cache(None)
 def bins_case(nb):
     cat = synth.uniform_catalogue(40 + nb, 900, 40.0)
     edges = synth.log_edges(1.0, 25.0, nb)
