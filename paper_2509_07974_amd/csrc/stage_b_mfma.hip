@@ -33,7 +33,9 @@
 // The split Y operand depends on (n2, centre) only, so in the mixed paths it
 // is formed once per group by yprep_kernel (conjugated, scaled, split into
 // hi/lo and laid out in MFMA lane order for every 32-centre chunk) instead
-// of once per (n2, n3) workgroup; the contraction copies it into LDS.
+// of once per (n2, n3) workgroup; the contraction copies it into LDS.  The
+// mixed paths also carry the centre factor x on that operand (Y = x B, X = A),
+// which moves the complex product x A out of the (n2, n3) workgroups.
 #include "factors.hpp"
 #include "fpcf4_internal.hpp"
 
@@ -184,9 +186,9 @@ typedef unsigned u4 __attribute__((ext_vector_type(4)));   // 16 bytes: one H8
 // Entry (ks, m, lane) holds row r = 16 m + lane % 16 of (mu, re/im, b2) and
 // centres 16 ks + 4 (lane / 16) + (0..3) of the chunk, as
 // [ y_r, -y_i ] (real-output rows) or [ y_i, y_r ] (imaginary-output rows)
-// per centre, y = B^mu(b2, n2) (conjugated where the factor table says so)
-// times the power-of-two scale of b2; rows past the used ones and centres
-// past the tile are zero.
+// per centre, y = x B^mu(b2, n2) (x the centre factor, both conjugated where
+// the factor table says so) times the power-of-two scale of b2; rows past the
+// used ones and centres past the tile are zero.
 __host__ __device__ constexpr int yprep_slots(int nmu, int nbc) { return (KC / 16) * mt_of(nmu, nbc) * 64; }
 inline size_t yprep_bytes_for(int nbc, int nmax, int64_t ncent) {
   const int64_t nchunk = (ncent + KC - 1) / KC;
@@ -198,9 +200,22 @@ inline size_t yprep_bytes_for(int nbc, int nmax, int64_t ncent) {
 // registers across the compute of the previous chunk (software pipelining).
 template <typename T, int NXS, int NYS>
 struct PrefetchP {
-  C2<T> xc[NXS], av[NXS], cv[NXS];
+  C2<T> av[NXS], cv[NXS];
   u4 yh[NYS], yl[NYS];
 };
+
+// Power-of-two operand scales of the mixed paths from the stage (a) maxima
+// (component maxima per bin; [32] |w g|, [33] w): Y = x B is below
+// 2 max|x| max|B| per component and is scaled below 2^14; X = A and Z = C
+// are below 1.5 max per component and are scaled below 2^6, so that the
+// Khatri-Rao products X Z stay below 2^13 (fp16 max 65504).
+__device__ __forceinline__ float y_scale(const unsigned* M, int xkind, int famB, int b2) {
+  const float mx = __uint_as_float(M[xkind == X_W ? 33 : 32]);
+  return pow2_below(2.0f * mx * __uint_as_float(M[famB + b2]), 14);
+}
+__device__ __forceinline__ float xz_scale(const unsigned* M, int fam, int b) {
+  return pow2_below(1.5f * __uint_as_float(M[fam + b]), 6);
+}
 
 template <int PREC, int G, int NBC>
 __global__ __launch_bounds__(256) void yprep_kernel(BArgs a) {
@@ -233,14 +248,23 @@ __global__ __launch_bounds__(256) void yprep_kernel(BArgs a) {
     const int mi = r / (2 * nb), part = (r % (2 * nb)) / nb, b2 = r % nb;
     const int row = (mi ? rowB1 : rowB0) * nb + b2;
     const bool cj = mi ? F1.B.conj : F0.B.conj;
-    const float sy = pow2_below(__uint_as_float(a.maxima[famB + b2]), 14);
+    const float sy = y_scale(a.maxima, F0.x, famB, b2);
     const float* rec = reinterpret_cast<const float*>(a.s.rec);
+    const C2<float>* xg = reinterpret_cast<const C2<float>*>(a.xg);
+    const float* xw = reinterpret_cast<const float*>(a.xw);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t c = ch * KC + 16 * ks + 4 * (l >> 4) + u;
       C2<float> y{0.f, 0.f};
-      if (c < ncent) y = ldrec(rec, (int64_t)row, a.ldc, (int)c);
-      if (cj) y.i = -y.i;
+      if (c < ncent) {
+        C2<float> b = ldrec(rec, (int64_t)row, a.ldc, (int)c);
+        C2<float> xc = F0.x == X_W ? C2<float>{xw[c], 0.f} : xg[c];
+        if (cj) b.i = -b.i;
+        if (F0.x == X_GC) xc.i = -xc.i;
+        // explicit fused forms: the rounding does not depend on how the
+        // compiler would contract the expression
+        y = {__builtin_fmaf(xc.r, b.r, -(xc.i * b.i)), __builtin_fmaf(xc.r, b.i, xc.i * b.r)};
+      }
       v[2 * u] = (part ? y.i : y.r) * sy;
       v[2 * u + 1] = (part ? y.r : -y.i) * sy;
     }
@@ -307,14 +331,12 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
 
   if (tid < 16) {
     const unsigned* M = a.maxima;
-    const float mx = __uint_as_float(M[F0.x == X_W ? 33 : 32]);
-    // |X| = |x A| <= 2 max|x| max|A|, |Z| <= 1.5 max|C| (component maxima);
-    // X and Z below 2^6 keep |X Z| below 2^12, Y below 2^14 (fp16 max 65504)
+    // the scales yprep_kernel and the staging below apply (undone exactly at the end)
     float sx = 1.0f, sy = 1.0f, sz = 1.0f;
     if (tid < nb) {
-      sx = pow2_below(2.0f * mx * __uint_as_float(M[famA + tid]), 6);
-      sy = pow2_below(__uint_as_float(M[famB + tid]), 14);
-      sz = pow2_below(1.5f * __uint_as_float(M[famC + tid]), 6);
+      sx = xz_scale(M, famA, tid);
+      sy = y_scale(M, F0.x, famB, tid);
+      sz = xz_scale(M, famC, tid);
     }
     sc_lds[0][tid] = sx;
     sc_lds[1][tid] = sy;
@@ -322,8 +344,6 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
   }
 
   // ---- staging: global -> registers (issue), registers -> LDS (commit)
-  const C2<float>* xg = reinterpret_cast<const C2<float>*>(a.xg) + cbase;
-  const float* xw = reinterpret_cast<const float*>(a.xw) + cbase;
   PrefetchP<float, NXS, NYS> pf;
   // this thread's Y slots (K-step, row tile, lane): 16-byte copies from the
   // split operand of this n2 (yprep_kernel)
@@ -347,8 +367,6 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
       const int slot = tid + NT * h;           // (bin, centre) slot of X and Z
       const int b = slot / KC, c = c0 + slot % KC;
       const int bl = b < nb ? b : nb - 1, cl = c < ncent ? c : ncent - 1;
-      if (F0.x == X_W) pf.xc[h] = {xw[cl], 0.f};
-      else pf.xc[h] = xg[cl];
       pf.av[h] = ldrec(rec, (int64_t)rowA * nb + bl, ldc, cl);
       pf.cv[h] = ldrec(rec, (int64_t)rowC * nb + bl, ldc, cl);
     }
@@ -365,16 +383,12 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
       const int slot = tid + NT * h;
       const int b = slot / KC, cc = slot % KC;
       if (b < nb) {
-        C2<float> xc = pf.xc[h], av = pf.av[h], cv = pf.cv[h];
-        if (F0.x == X_GC) xc.i = -xc.i;
+        C2<float> av = pf.av[h], cv = pf.cv[h];
         if (F0.A.conj) av.i = -av.i;
         if (F0.C.conj) cv.i = -cv.i;
         const bool live = c0 + cc < ncent;
         const float sx = live ? sc_lds[0][b] : 0.f, sz = live ? sc_lds[2][b] : 0.f;
-        // explicit fused forms: the rounding does not depend on how the
-        // compiler would contract the expression
-        Xs[buf][b][cc] = {__builtin_fmaf(xc.r, av.r, -(xc.i * av.i)) * sx,
-                          __builtin_fmaf(xc.r, av.i, xc.i * av.r) * sx};
+        Xs[buf][b][cc] = {av.r * sx, av.i * sx};
         Zs[buf][b][cc] = {cv.r * sz, cv.i * sz};
       }
     }
