@@ -83,6 +83,22 @@ def test_tiles_with_ragged_tail_match_single_tile(fp):
     assert np.all(rel_per_mu(many, one) < 1e-13)
 
 
+def test_mixed_tiles_with_ragged_tail(fp):
+    """Mixed path in ragged tiles of 333 centres (the split Y operand of each
+    group is formed per tile, every centre slice and chunk boundary moves):
+    within the oracle bar, and within the blocked binary32 accumulation of the
+    contraction (blocks of 512 centres start at each tile's first centre) of
+    the single-tile result; the same tiling twice is bitwise equal."""
+    cat, edges, nmax = c0()
+    for prec in ("fp16", "bf16"):
+        one = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision=prec)
+        many = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision=prec, tile_centers=333)
+        again = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision=prec, tile_centers=333)
+        assert np.all(rel_per_mu(many, c0_ref(True)) < TOL[prec])
+        assert np.all(rel_per_mu(many, one) < 2e-6), prec
+        assert np.array_equal(many, again)
+
+
 def test_centre_subset(fp):
     cat, edges, nmax = c0()
     idx = np.random.default_rng(5).choice(cat.n, 97, replace=False)
