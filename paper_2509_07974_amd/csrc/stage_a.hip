@@ -305,41 +305,68 @@ __device__ __forceinline__ void acc_fields(T* acc, const T* val, T pr, T pi) {
   }
 }
 
+template <typename T>
+__device__ __forceinline__ T fmadd(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+
+// Sign of the power a pass holds at offset d = K - K0 of its chain:
+// +, +, -, -, +, +, ...  The units of order K accumulate that multiple of
+// their sums; the epilogue multiplies it back.
+__host__ __device__ constexpr int chain_sign(int d) { return ((d >> 1) & 1) ? -1 : 1; }
+
 // The power chain alternates a complex product z^(K+1) = z^K z with the
 // two-term recurrence z^(K+1) = 2 Re(z) z^K - z^(K-1) (two fused
 // multiply-adds instead of four).  A recurrence step from exact powers errs
 // by (|z|^2 - 1) z^(K-1), independent of the angle, and the interleaved
 // products keep later errors from growing: in binary32 the powers up to
 // z^26 stay within 1.4x the error of the all-product chain.
+// Every step is a multiply-add with no negated operand (-Im z comes with
+// the neighbour, -2 Re z is formed once per neighbour), so that it encodes as
+// the two-operand accumulate (VOP2), which can issue in the same cycle as
+// another VALU instruction; the recurrence then yields -z^(K+1), hence the
+// alternating chain_sign.
 template <typename T, int N, int K0, int K1, int K>
 __device__ __forceinline__ void acc_orders(T* acc, const T* val, T pr, T pi, T qr, T qi, T zr,
-                                           T zi, T c2) {
+                                           T zi, T nzi, T nc2) {
   acc_fields<T, N, K0, K1, K, 0>(acc, val, pr, pi);
   if constexpr (K < K1) {
     T tr, ti;
-    if constexpr (((K - K0) & 1) == 0) {
-      tr = pr * zr - pi * zi;
-      ti = pr * zi + pi * zr;
+    if constexpr (K == 0) {
+      tr = zr;   // z^0 z
+      ti = zi;
+    } else if constexpr (((K - K0) & 1) == 0) {
+      tr = fmadd(pr, zr, pi * nzi);
+      ti = fmadd(pr, zi, pi * zr);
     } else {
-      tr = c2 * pr - qr;
-      ti = c2 * pi - qi;
+      tr = fmadd(nc2, pr, qr);
+      ti = fmadd(nc2, pi, qi);
     }
-    acc_orders<T, N, K0, K1, K + 1>(acc, val, tr, ti, pr, pi, zr, zi, c2);
+    acc_orders<T, N, K0, K1, K + 1>(acc, val, tr, ti, pr, pi, zr, zi, nzi, nc2);
   }
 }
 
+// z^E by squaring; the first factor is taken as it is (no product with 1)
 template <typename T, int E>
 __device__ __forceinline__ void cpow(T zr, T zi, T& pr, T& pi) {
   pr = T(1);
   pi = T(0);
   T br = zr, bi = zi;
   int e = E;
+  bool one = true;
 #pragma unroll
   for (int it = 0; it < 6; ++it) {
     if (e & 1) {
-      const T tr = pr * br - pi * bi;
-      pi = pr * bi + pi * br;
-      pr = tr;
+      if (one) {
+        pr = br;
+        pi = bi;
+        one = false;
+      } else {
+        const T tr = pr * br - pi * bi;
+        pi = pr * bi + pi * br;
+        pr = tr;
+      }
     }
     e >>= 1;
     if (e) {
@@ -358,15 +385,16 @@ template <typename T> struct alignas(2 * sizeof(T)) Q2 { T x, y; };
 template <typename T> struct Nb {
   T zr, zi, a, b, c, d, e, v, w;
   T sr, si;   // z^K0 of the consuming pass, when the binning lane formed it
+  T nzi;      // -Im z
   T p3, q3, ea, eb, u;   // triple-block weights of a pseudo-galaxy (reduced catalogues)
 };
 
 // binary32 passes take their first power z^K0 from the ring (formed once per
 // neighbour by the lane that binned it); binary64 rings would not fit LDS
 template <typename T> constexpr bool kRingStarts = sizeof(T) == 4;
-// Exact binary32 ring: the weight w travels in the third component of the
-// start slots, so that every ring array a pass reads has the 16-byte stride
-// of q0 and one address serves all reads of a neighbour.  The reduced-
+// Exact binary32 ring: the weight w and -Im z travel in the third and fourth
+// components of the start slots, so that every ring array a pass reads has
+// the 16-byte stride of q0 and one address serves all reads of a neighbour.  The reduced-
 // catalogue kernel keeps separate 8-byte starts and w (its ring also holds
 // the triple-block weights, and the larger slots would cost occupancy).
 template <typename T, bool RED> constexpr bool kPackW = sizeof(T) == 4 && !RED;
@@ -394,7 +422,7 @@ __device__ __forceinline__ void add_pair(T* acc, bool valid, Nb<T> q) {
   } else {
     cpow<T, K0>(zr, zi, pr, pi);
   }
-  acc_orders<T, N, K0, K1, K0>(acc, val, pr, pi, T(0), T(0), zr, zi, T(2) * zr);
+  acc_orders<T, N, K0, K1, K0>(acc, val, pr, pi, T(0), T(0), zr, zi, q.nzi, T(-2) * zr);
   if constexpr (P0 && !is3(N)) {
     // triple-counting blocks: T_-8, T_-4 (weight (w g)^3), M_-4, M_0
     // (weight |w g|^2 w g) and U (weight w^3)
@@ -477,8 +505,12 @@ __device__ __forceinline__ void put_starts(SH& sh, unsigned slot, T zr, T zi, T 
     constexpr int D = Conf<T, N>::PP.k0[P] - Conf<T, N>::PP.k0[P - 1];
     T dr, di;
     cpow<T, D>(zr, zi, dr, di);
-    const T nr = pr * dr - pi * di, ni = pr * di + pi * dr;
-    if constexpr (SH::PACK) sh.qk[P - 1][slot] = Q4<T>{nr, ni, w, T(0)};
+    T nr = dr, ni = di;   // pass 1 starts at z^D itself
+    if constexpr (P > 1) {
+      nr = pr * dr - pi * di;
+      ni = pr * di + pi * dr;
+    }
+    if constexpr (SH::PACK) sh.qk[P - 1][slot] = Q4<T>{nr, ni, w, -zi};
     else sh.qk[P - 1][slot] = Q2<T>{nr, ni};
     put_starts<T, N, P + 1>(sh, slot, zr, zi, nr, ni, w);
   }
@@ -523,19 +555,24 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
   auto fetch = [&](unsigned slot) -> Nb<T> {
     const Q4<T> u = sh.q0[slot];
     const Q4<T> v = sh.q1[slot];
-    T sr = T(0), si = T(0), ww;
+    T sr = T(0), si = T(0), ww, nzi = -u.y;
     constexpr bool PK = kPackW<T, RED>;
     if constexpr (PASS > 0 && kRingStarts<T>) {
       const auto k = sh.qk[PASS - 1][slot];
       sr = k.x;
       si = k.y;
-      if constexpr (PK) ww = k.z;
+      if constexpr (PK) { ww = k.z; nzi = k.w; }
       else ww = sh.qw[slot];
     } else {
-      if constexpr (PK) ww = sh.qk[0][slot].z;
-      else ww = sh.qw[slot];
+      if constexpr (PK) {
+        const Q4<T> k = sh.qk[0][slot];
+        ww = k.z;
+        nzi = k.w;
+      } else {
+        ww = sh.qw[slot];
+      }
     }
-    Nb<T> q{u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w, ww, sr, si};
+    Nb<T> q{u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w, ww, sr, si, nzi};
     if constexpr (RED && PASS == 0) {
       const Q4<T> t = sh.q2[slot];
       q.p3 = t.x;
@@ -751,7 +788,7 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
               sh.qu[slot] = gc.u;
             }
             if constexpr (kRingStarts<T> && W > 1) put_starts<T, N, 1>(sh, slot, zr, zi, T(1), T(0), vw);
-            else if constexpr (kPackW<T, RED>) sh.qk[0][slot] = Q4<T>{T(0), T(0), vw, T(0)};
+            else if constexpr (kPackW<T, RED>) sh.qk[0][slot] = Q4<T>{T(0), T(0), vw, -zi};
             if constexpr (!RED) sh.q1[slot] = Q4<T>{va * va - vb * vb, T(2) * va * vb, va * va + vb * vb, vw * vw};
             if constexpr (!kPackW<T, RED>) sh.qw[slot] = vw;
           }
@@ -795,7 +832,7 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
       float gmax = 0.f, wmax = 0.f;   // block maxima for the fp16 operand scaling
       auto su = [&](int f, int k, int part) -> double {
         if (k == 0 && part == 1) return 0.0;
-        return S[uidx(N, K0, f, k) + part];
+        return (double)chain_sign(k - K0) * S[uidx(N, K0, f, k) + part];
       };
       for (int e = (int)lane; e < L.mpc; e += 64) {
         double re = 0.0, im = 0.0;
