@@ -283,6 +283,21 @@ __global__ __launch_bounds__(256) void yprep_kernel(BArgs a) {
 // ---------------------------------------------------------------------------
 // mixed precision
 // ---------------------------------------------------------------------------
+// Workgroups are dealt to the 8 XCDs round-robin in dispatch order (x
+// fastest, then y).  The contraction kernels renumber them so that every
+// XCD runs a contiguous range of (slice, n2, n3): the 2n+1 workgroups of one
+// (slice, n2), which stage the same prepared Y chunks, then run on one XCD
+// at the same time and share its L2.  A bijection of the grid onto itself.
+__device__ __forceinline__ void xcd_block(int& bx, int& by) {
+  const int gx = (int)gridDim.x, total = gx * (int)gridDim.y;
+  const int lin = (int)blockIdx.y * gx + (int)blockIdx.x;
+  const int per = total >> 3, rem = total & 7;
+  const int x = lin & 7, i = lin >> 3;
+  const int l = x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+  bx = l % gx;
+  by = l / gx;
+}
+
 template <int PREC, int G, int NBC>
 __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
   typedef typename Half8<PREC>::type H8;
@@ -298,7 +313,9 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
   constexpr int NYS = (KS * MT * 64 + NT - 1) / NT;   // Y operand slots per thread
   const int nb = a.s.nb, n = a.s.nmax, nn = 2 * n + 1;
   const Layout L = make_layout(n);
-  const int lb = (int)blockIdx.x;
+  int bx, by;
+  xcd_block(bx, by);
+  const int lb = bx;
   const int n2 = lb / nn - n;
   const int n3 = lb % nn - n;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -306,13 +323,13 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
   // column tiles of this wave: T = wr + WB t.  When the tiles do not split
   // evenly, the wave holding one more is rotated with the block index, so
   // that co-resident workgroups put their longer waves on different SIMDs.
-  const int wr = (wv + (int)blockIdx.x) & (WB - 1);
+  const int wr = (wv + bx) & (WB - 1);
   const int mrows = GR.nmu * 2 * nb;
   const int ncols = nb * nb;
   const int ntiles = (ncols + 15) >> 4;
   // centre slice of this workgroup (blockIdx.y): centres [cbase, cbase + ncent)
   const int per = contract_slice_len(a.s.ncent, (int)gridDim.y);
-  const int cbase = (int)blockIdx.y * per;
+  const int cbase = by * per;
   const int ncent = imax(0, imin(a.s.ncent - cbase, per));
   const float* rec = reinterpret_cast<const float*>(a.s.rec) + 2 * (int64_t)cbase;
   const int ldc = a.ldc;
@@ -508,7 +525,7 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
         const int64_t o = (((((int64_t)mu * nb + b1) * nb + b2) * nb + b3) * nn + (n2 + n)) * nn + (n3 + n);
         const double v = acc64[m][t][r] * unscale;
         if (gridDim.y == 1) a.s.ups[2 * o + part] += v;
-        else a.s.part[(int64_t)blockIdx.y * ups2 + 2 * o + part] = v;
+        else a.s.part[(int64_t)by * ups2 + 2 * o + part] = v;
       }
     }
   }
@@ -529,7 +546,9 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
   constexpr int NXS = (NBC * KC + NT - 1) / NT;  // (bin, centre) staging slots per thread
   const int nb = a.s.nb, n = a.s.nmax, nn = 2 * n + 1;
   const Layout L = make_layout(n);
-  const int lb = (int)blockIdx.x;
+  int bx, by;
+  xcd_block(bx, by);
+  const int lb = bx;
   const int n2 = lb / nn - n;
   const int n3 = lb % nn - n;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -537,12 +556,12 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
   // column tiles of this wave: T = wr + WB t.  When the tiles do not split
   // evenly, the wave holding one more is rotated with the block index, so
   // that co-resident workgroups put their longer waves on different SIMDs.
-  const int wr = (wv + (int)blockIdx.x) & (WB - 1);
+  const int wr = (wv + bx) & (WB - 1);
   const int mrows = GR.nmu * 2 * nb;
   const int ncols = nb * nb;
   const int ntiles = (ncols + 15) >> 4;
   const int per = contract_slice_len(a.s.ncent, (int)gridDim.y);
-  const int cbase = (int)blockIdx.y * per;
+  const int cbase = by * per;
   const int ncent = imax(0, imin(a.s.ncent - cbase, per));
   const double* rec = reinterpret_cast<const double*>(a.s.rec) + 2 * (int64_t)cbase;
   const int ldc = a.ldc;
@@ -679,7 +698,7 @@ __global__ __launch_bounds__(512) void contract_f64_kernel(BArgs a) {
         const int mu = mi ? GR.mu[1] : GR.mu[0];
         const int64_t o = (((((int64_t)mu * nb + b1) * nb + b2) * nb + b3) * nn + (n2 + n)) * nn + (n3 + n);
         if (gridDim.y == 1) a.s.ups[2 * o + part] += acc[m][t][r];
-        else a.s.part[(int64_t)blockIdx.y * ups2 + 2 * o + part] = acc[m][t][r];
+        else a.s.part[(int64_t)by * ups2 + 2 * o + part] = acc[m][t][r];
       }
     }
   }
