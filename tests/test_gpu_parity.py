@@ -260,3 +260,22 @@ def test_grf1m_sampled_centres(fp, prec):
     err = rel_per_mu(got, ref)
     print(prec, err)
     assert np.all(err < TOL[prec]), err
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp16", 2e-6)])
+def test_centre_slices_add_up(fp, prec, tol):
+    """Upsilon is a sum over centres.  40000 centres in one call (at nmax 10
+    the contraction cuts them into 4 centre slices of 10016, 10016, 10016 and
+    9952, each on workgroups of its own, added in slice order) equal the sum
+    of four calls over 10000 of them (one slice each).  The mixed paths sum
+    blocks of 512 centres in binary32 from each slice's first centre and
+    scale their 16-bit operands by each call's own maxima, so they agree to
+    that accuracy (5e-7 at these sizes); the FP64 path to rounding."""
+    cat, edges, nmax = grf1m()
+    idx = np.random.default_rng(17).choice(cat.n, 40000, replace=False)
+    whole = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision=prec, centers=idx)
+    parts = sum(fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision=prec, centers=idx[k::4])
+                for k in range(4))
+    err = rel_per_mu(whole, parts)
+    print(prec, err)
+    assert np.all(err < tol), err
