@@ -327,7 +327,7 @@ __global__ __launch_bounds__(512) void contract_mixed_kernel(BArgs a) {
   const int mrows = GR.nmu * 2 * nb;
   const int ncols = nb * nb;
   const int ntiles = (ncols + 15) >> 4;
-  // centre slice of this workgroup (blockIdx.y): centres [cbase, cbase + ncent)
+  // centre slice of this workgroup (by): centres [cbase, cbase + ncent)
   const int per = contract_slice_len(a.s.ncent, (int)gridDim.y);
   const int cbase = by * per;
   const int ncent = imax(0, imin(a.s.ncent - cbase, per));
