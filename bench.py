@@ -29,6 +29,7 @@ PEAK_FP64_VALU = 78.6e12      # published vector fp64 peak
 PEAK_F16_MFMA = 2.5e15        # published dense fp16 / bf16 matrix peak
 PEAK_FP64_MFMA = 78.6e12      # published fp64 matrix peak
 STAGE_A_SRC = os.path.join(ROOT, "paper_2509_07974_amd", "csrc", "stage_a.hip")
+STAGE_A_INPUT_SRCS = [os.path.join(ROOT, "paper_2509_07974_amd", "csrc", f) for f in ("api.hip", "cells.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_a_grf1m_traffic.txt")
 
 
@@ -56,10 +57,21 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
+def input_source_hash() -> str:
+    """sha256 over the sources that decide what stage (a) reads: the planner
+    (cell grid) and the cell-list build."""
+    import hashlib
+    h = hashlib.sha256()
+    for src in STAGE_A_INPUT_SRCS:
+        with open(src, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def stage_a_traffic():
     """HBM bytes per stage (a) launch from the committed rocprofv3 counter
-    summary, or None if it is missing or was taken on another kernel
-    source."""
+    summary, or None if it is missing or was taken on another kernel, planner
+    or cell-list source."""
     try:
         kv = {}
         with open(TRAFFIC_FILE) as f:
@@ -68,6 +80,8 @@ def stage_a_traffic():
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
         if kv.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        if kv.get("input_source_sha256") != input_source_hash():
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):

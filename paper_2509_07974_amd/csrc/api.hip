@@ -315,9 +315,13 @@ fpcf4_status request_init(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   HIPCHK(hipStreamSynchronize(s));
   if (hbad) return fail(FPCF4_E_INVALID_ARG, "catalogue has %u non-finite entries", hbad);
 
-  // cell grid: side ~ outer edge / 24 (<= ~51 cell rows per annulus), capped cell count
+  // cell grid: side ~ outer edge / 48 (<= ~99 cell rows per annulus, two row
+  // tables of 64), capped cell count.  Finer cells walk fewer candidates
+  // outside the bin, for more and shorter row segments (10^6 galaxies on
+  // 600x600 arcmin, 12 bins 1-100: 1.14 candidates per in-bin pair, 1.28 at
+  // outer edge / 24).
   const double rmax = bins->edges[P.nb];
-  double h = rmax / 24.0;
+  double h = rmax / 48.0;
   const double wx = bb[1] - bb[0], wy = bb[3] - bb[2];
   for (;;) {
     const double ncx = std::floor(wx / h) + 1.0, ncy = std::floor(wy / h) + 1.0;
