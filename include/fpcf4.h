@@ -29,8 +29,12 @@
  *  - Position angles phi_ij = atan2(y_j - y_i, x_j - x_i), counter-clockwise
  *    from +x (Sect. 2.2).  No periodic wrap.
  *  - Device pointers are HIP device pointers on the current device; `stream`
- *    is a hipStream_t (NULL = the library's internal stream).  Calls are
- *    synchronous: results are complete in the output buffer on return.
+ *    is a hipStream_t on which every device operation of the call is
+ *    queued (NULL = the HIP null stream).  The library does not order that
+ *    stream after work the caller queued on other streams: inputs written on
+ *    another stream must be complete (or the stream made to wait) before the
+ *    call.  The estimate calls are synchronous: results are complete in the
+ *    output buffer on return.
  */
 #ifndef FPCF4_H
 #define FPCF4_H
@@ -99,7 +103,7 @@ typedef struct {
                                   NULL = all.  Every galaxy stays a neighbour. */
   int64_t ncenters;
   int64_t tile_centers;        /* centres per stage tile; 0 = planner choice  */
-  void *stream;                /* hipStream_t or NULL                         */
+  void *stream;                /* hipStream_t, or NULL for the null stream    */
 } fpcf4_options;
 
 /* Number of complex128 elements of the output tensor:
@@ -123,14 +127,15 @@ int64_t fpcf4_output3_elems(int32_t nbins, int32_t nmax);
 /* Shear 3PCF multipoles through the order-N construction of the appendix on
  * N-th order shear statistics, at N = 3 (natural components Gamma_0..Gamma_3
  * from the beta matrix, generalised x-projection zeta_0 = (phi_1 + phi_2)/2):
- *   Upsilon_{mu,n}(T1, T2) = sum_i x_i F1 F2 with
+ *   Upsilon_{mu,n}(T1, T2) = s_mu sum_i x_i F1 F2 with
  *   mu 0: x = w g,  F1 = G_{n-3},         F2 = G_{-n-3};
  *   mu 1: x = conj(w g), F1 = G_{n-1},    F2 = G_{-n-1};
  *   mu 2: x = w g,  F1 = conj G_{-n-1},   F2 = G_{-n-3};
  *   mu 3: x = w g,  F1 = G_{n-3},         F2 = conj G_{n-1};
  *   N   : x = w,    F1 = W_n,             F2 = W_{-n}
- * (the multipole formula as printed in that appendix, without the sign a
- * product of three projected shears -gamma_c e^{-2i zeta} would carry).
+ * with s_mu = -1 for mu = 0..3 and +1 for N: the natural components are
+ * products of three projected shears gamma = -gamma_c e^{-2i zeta} (Sect.
+ * 2.1), whose factor (-1)^3 the block formula of that appendix leaves out.
  * The blocks come from the stage (a) records of order ceil(nmax / 2), so the
  * pair stage is shared with the 4PCF path.
  * opts->nmax is the largest 3PCF multipole, 0 <= nmax <= FPCF4_NMAX3_SUPPORTED;

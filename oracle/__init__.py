@@ -5,7 +5,8 @@ and the ``cpu_baseline`` leg of ``bench.py``; never by the library.
 """
 from .estimator import (NCORR, FACTORS, TABLE1, family_orders, squared_edges,
                         centre_neighbours, bin_counts, centre_multipoles,
-                        multipoles, contract, upsilon, upsilon_parallel)
+                        multipoles, contract, upsilon, upsilon_parallel, abs_bound,
+                        abs_bound_parallel)
 from .brute import brute_upsilon, brute_angular_bins
 from .natural import (angular_integrals, binned_from_multipoles, natural_components,
                       natural_components_triplets)

@@ -281,9 +281,61 @@ def upsilon(x, y, g1, g2, w, edges, nmax, centers=None, distinct=True,
     return out
 
 
+def abs_bound(x, y, g1, g2, w, edges, centers=None, order=4):
+    """Scale of every term of the estimator, per radial-bin tuple: the sum over
+    centres of the absolute values of the centre factor and of the per-bin
+    block factors.  Since |e^{i k phi}| = 1, each block satisfies
+    |F_k(theta_i, Theta_b)| <= sum_{j in b} |v_j|, so by the triangle
+    inequality every element of Upsilon (raw or over distinct quadruplets, a
+    subset of the terms) is bounded by
+      S[0](b1,b2,b3) = sum_i |w_i gamma_i| Gbar_i(b1) Gbar_i(b2) Gbar_i(b3)
+    for the shear correlators and by S[1] (the same with w, Wbar) for N,
+    Gbar_i(b) = sum_{j in b} |w_j gamma_j|, Wbar_i(b) = sum_{j in b} |w_j|.
+    With positive weights, S[1] equals the raw N_{(0,0)}.  order=3 gives the
+    two-bin analogue [2, nb, nb] for the shear 3PCF."""
+    x, y, g1, g2, w = (np.asarray(a, dtype=np.float64) for a in (x, y, g1, g2, w))
+    e2 = squared_edges(edges)
+    nb = e2.size - 1
+    if centers is None:
+        centers = range(x.size)
+    ag = np.abs(w * (g1 + 1j * g2))
+    aw = np.abs(w)
+    out = np.zeros((2,) + (nb,) * (order - 1))
+    for i in centers:
+        i = int(i)
+        j, b, _, _ = centre_neighbours(x, y, e2, i)
+        for k, (xc, v) in enumerate(((ag[i], ag), (aw[i], aw))):
+            s = np.bincount(b, weights=v[j], minlength=nb)
+            t = xc * s
+            for _ in range(order - 2):
+                t = np.multiply.outer(t, s)
+            out[k] += t
+    return out
+
+
 def _worker(args):
     x, y, g1, g2, w, edges, nmax, centers, distinct = args
     return upsilon(x, y, g1, g2, w, edges, nmax, centers, distinct)
+
+
+def _bound_worker(args):
+    x, y, g1, g2, w, edges, centers, order = args
+    return abs_bound(x, y, g1, g2, w, edges, centers, order)
+
+
+def abs_bound_parallel(x, y, g1, g2, w, edges, centers, order=4, processes=1):
+    """``abs_bound`` over centre chunks in a process pool, added in chunk order."""
+    centers = np.asarray(centers, dtype=np.int64)
+    if processes <= 1:
+        return abs_bound(x, y, g1, g2, w, edges, centers, order)
+    import multiprocessing as mp
+    chunks = np.array_split(centers, processes)
+    with mp.get_context("fork").Pool(processes) as pool:
+        res = pool.map(_bound_worker, [(x, y, g1, g2, w, edges, c, order) for c in chunks])
+    out = res[0]
+    for r in res[1:]:
+        out = out + r
+    return out
 
 
 def upsilon_parallel(x, y, g1, g2, w, edges, nmax, centers=None, distinct=True,

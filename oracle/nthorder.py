@@ -28,11 +28,13 @@ statistics" of Porth et al. (2025):
 5. N = 3, distinct pairs of neighbours (j != k): the j = k terms of the
    double sum, present only when both slots share a bin, are subtracted.
 
-Reading: the printed multipole formula of that appendix carries no sign,
-whereas a product of N projected shears gamma = -gamma_c e^{-2 i zeta}
-carries (-1)^N.  The formula is followed as printed, i.e. the triplet
-summand uses the rotated shears gamma_c e^{-2 i zeta} (for N = 4 both
-conventions agree).
+Reading: the appendix writes the multipoles through the blocks G and W and
+only states the argument of the exponent; the natural components themselves
+are products of N projected shears gamma = -gamma_c e^{-2 i zeta} (Sect. 2.1),
+which carry the factor (-1)^N that the printed block formula omits.  The
+definition decides: every shear component of order N is the block product
+times (-1)^N (no change for N = 4; a minus sign for the N = 3 shear
+components, none for the normalisation, whose summand has no shear).
 
 All arithmetic is numpy float64 / complex128.
 """
@@ -42,6 +44,7 @@ import itertools
 
 import numpy as np
 
+from .brute import projected
 from .estimator import check_inputs, centre_neighbours, squared_edges
 
 
@@ -130,6 +133,7 @@ def upsilon_n(x, y, g1, g2, w, edges, N, nmax, centers=None, coeff=arg_coefficie
             for l, c in enumerate(coeff(r, ns)):
                 orders.add(c if r[l + 1] > 0 else -c)
         orders.update(norm_coefficients(ns))
+    sign = (-1.0) ** N          # the product of N projected shears -gamma_c e^{-2 i zeta}
     for i in centers:
         i = int(i)
         sel, b, dx, dy = centre_neighbours(x, y, e2, i)
@@ -137,7 +141,7 @@ def upsilon_n(x, y, g1, g2, w, edges, N, nmax, centers=None, coeff=arg_coefficie
             continue
         phi = np.arctan2(dy, dx)
         blk = _slot_blocks(phi, b, w[sel] * gam[sel], w[sel], nb, sorted(orders))
-        xg = w[i] * gam[i]
+        xg = sign * w[i] * gam[i]
         for ns in nvecs:
             idx = tuple(n + nmax for n in ns)
             for mu, r in enumerate(B):
@@ -179,7 +183,7 @@ def upsilon3(x, y, g1, g2, w, edges, nmax, centers=None, distinct=True, coeff=ar
             continue
         phi = np.arctan2(dy, dx)
         wg = w[sel] * gam[sel]
-        xg = w[i] * gam[i]
+        xg = -w[i] * gam[i]          # (-1)^3 of three projected shears
         for mu, r in enumerate(B):
             # j = k: both neighbour factors taken at the same galaxy; the
             # phase is the sum of the two slot coefficients (independent of n)
@@ -201,12 +205,13 @@ def upsilon3(x, y, g1, g2, w, edges, nmax, centers=None, distinct=True, coeff=ar
 
 
 def brute_upsilon3(x, y, g1, g2, w, edges, nmax, centers=None, distinct=True):
-    """Triplet-by-triplet sum: for every centre i and ordered neighbour pair
-    (j, k) with theta_ij in Theta_1, theta_ik in Theta_2 (j != k if
-    distinct), the product of the rotated shears gamma_c e^{-2 i zeta}
-    (conjugated where beta = -1) with zeta_0 = (phi_ij + phi_ik)/2,
-    zeta_1 = phi_ij, zeta_2 = phi_ik, times w_i w_j w_k and
-    e^{-i n phi_ijk}, phi_ijk = phi_ik - phi_ij.  O(N m^2): tiny inputs."""
+    """Triplet-by-triplet sum from the definitions: for every centre i and
+    ordered neighbour pair (j, k) with theta_ij in Theta_1, theta_ik in
+    Theta_2 (j != k if distinct), the product of the projected shears
+    gamma(X; zeta) = -gamma_c e^{-2 i zeta} of Sect. 2.1 (conjugated where
+    beta = -1) with zeta_0 = (phi_ij + phi_ik)/2, zeta_1 = phi_ij,
+    zeta_2 = phi_ik, times w_i w_j w_k and e^{-i n phi_ijk},
+    phi_ijk = phi_ik - phi_ij.  O(N m^2): tiny inputs."""
     x, y, g1, g2, w = (np.asarray(a, dtype=np.float64) for a in (x, y, g1, g2, w))
     B = beta_matrix(3)
     e2 = squared_edges(edges)
@@ -234,9 +239,9 @@ def brute_upsilon3(x, y, g1, g2, w, edges, nmax, centers=None, distinct=True):
         if J.size == 0:
             continue
         p1, p2 = phi[J], phi[K]
-        rot = (gam[i] * np.exp(-1j * (p1 + p2)),
-               gam[nbr][J] * np.exp(-2j * p1),
-               gam[nbr][K] * np.exp(-2j * p2))
+        rot = (projected(gam[i], (p1 + p2) / 2),
+               projected(gam[nbr][J], p1),
+               projected(gam[nbr][K], p2))
         wt = w[i] * w[nbr][J] * w[nbr][K]
         E = np.exp(-1j * np.multiply.outer(p2 - p1, ns))
         bj, bk = b[nbr][J], b[nbr][K]

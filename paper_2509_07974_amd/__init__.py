@@ -16,7 +16,8 @@ from . import _lib
 from ._lib import (FP64, MIXED_FP16, MIXED_BF16, MEM_HOST, MEM_DEVICE, NMAX_SUPPORTED,
                    NBINS_SUPPORTED, Fpcf4Error, check, lib)
 
-__all__ = ["estimate_4pcf_multipoles", "estimate_3pcf_multipoles", "debug_multipoles", "to_natural",
+__all__ = ["estimate_4pcf_multipoles", "estimate_3pcf_multipoles",
+           "debug_multipoles", "to_natural",
            "to_natural_triplets", "natural_blocks", "plan", "Request",
            "profile_enable", "profile_read",
            "PRECISIONS", "Fpcf4Error", "output_shape", "output3_shape", "lib", "version"]
@@ -35,6 +36,52 @@ def output_shape(nbins: int, nmax: int):
 
 def output3_shape(nbins: int, nmax: int):
     return (5, nbins, nbins, 2 * nmax + 1)
+
+
+def _stream_handle(stream):
+    """Raw hipStream_t of `stream` (a torch stream object or an integer handle)."""
+    if stream is None:
+        return None
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+def _order_after_current(stream, device):
+    """Make the caller's stream wait for the work torch has queued on its
+    current stream (the input copies and the output allocation), so that the
+    library, which runs on `stream`, never reads inputs before they are
+    written or writes memory torch's allocator handed out on another stream."""
+    import torch
+    cur = torch.cuda.current_stream(device)
+    if stream is None or stream == cur.cuda_stream:
+        return
+    torch.cuda.ExternalStream(stream, device=device).wait_stream(cur)
+
+
+def _check_out(out, shape, device, torch_device=None):
+    """Reject an `out` buffer the library could not write safely: wrong
+    shape, dtype, layout or memory space (the library writes
+    prod(shape) complex128 values through a raw pointer)."""
+    shape = tuple(int(d) for d in shape)
+    if device:
+        import torch
+        if not isinstance(out, torch.Tensor) or not out.is_cuda or out.device != torch_device:
+            raise ValueError(f"out must be a torch tensor on {torch_device}")
+        if out.dtype != torch.complex128:
+            raise ValueError(f"out must be complex128, not {out.dtype}")
+        if tuple(out.shape) != shape:
+            raise ValueError(f"out has shape {tuple(out.shape)}, expected {shape}")
+        if not out.is_contiguous():
+            raise ValueError("out must be contiguous")
+        return out
+    if not isinstance(out, np.ndarray):
+        raise ValueError("out must be a NumPy array for host inputs")
+    if out.dtype != np.complex128:
+        raise ValueError(f"out must be complex128, not {out.dtype}")
+    if out.shape != shape:
+        raise ValueError(f"out has shape {out.shape}, expected {shape}")
+    if not out.flags.c_contiguous or not out.flags.writeable:
+        raise ValueError("out must be C-contiguous and writeable")
+    return out
 
 
 def _is_torch_device(a) -> bool:
@@ -62,10 +109,12 @@ class _Marshal:
             self.keep += dev
             ptrs = [a.data_ptr() for a in dev]
             mem = MEM_DEVICE
+            stream = _stream_handle(stream)
             if stream is None:
                 stream = torch.cuda.current_stream(dev[0].device).cuda_stream
             self.torch_device = dev[0].device
         else:
+            stream = _stream_handle(stream)
             host = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in arrs]
             n = host[0].size
             if any(a.size != n for a in host):
@@ -93,11 +142,24 @@ class _Marshal:
                 cptr, nc = ca.ctypes.data, ca.size
         self.ncent = nc if centers is not None else n
         self.nmax = int(nmax)
+        self.stream = stream
         self.opts = _lib.Options(self.nmax, prec, 1 if subtract_degenerate else 0, 0, cptr, nc,
                                  int(tile_centers), stream)
 
     def refs(self):
         return C.byref(self.cat), C.byref(self.bins), C.byref(self.opts)
+
+    def output(self, shape, out):
+        """The output buffer (validated `out`, or a new one), after ordering
+        the library's stream behind torch's current stream."""
+        if self.device:
+            import torch
+            res = (_check_out(out, shape, True, self.torch_device) if out is not None
+                   else torch.empty(shape, dtype=torch.complex128, device=self.torch_device))
+            _order_after_current(self.stream, self.torch_device)
+            return res, res.data_ptr(), MEM_DEVICE
+        res = _check_out(out, shape, False) if out is not None else np.empty(shape, dtype=np.complex128)
+        return res, res.ctypes.data, MEM_HOST
 
 
 def estimate_4pcf_multipoles(x, y, g1, g2, w, edges, nmax: int, precision="fp64",
@@ -107,23 +169,19 @@ def estimate_4pcf_multipoles(x, y, g1, g2, w, edges, nmax: int, precision="fp64"
     complex128 array [9, nb, nb, nb, 2nmax+1, 2nmax+1] (NumPy for host inputs,
     a torch tensor on the inputs' device for device inputs).
     tree = (delta1, nlevels, rmin) selects the tree approximation (reduced
-    catalogues on grids delta1 * 2^(d-1); mixed precisions only)."""
+    catalogues on grids delta1 * 2^(d-1); mixed precisions only).
+    out: optional preallocated result (same type, shape, complex128,
+    contiguous, on the inputs' device); stream: a torch stream or a raw
+    hipStream_t (default: torch's current stream)."""
     m = _Marshal(x, y, g1, g2, w, edges, nmax, precision, subtract_degenerate, centers,
                  tile_centers, stream)
-    shape = output_shape(m.nbins, m.nmax)
+    res, ptr, mem = m.output(output_shape(m.nbins, m.nmax), out)
     if tree is not None:
         delta1, nlevels, rmin = tree
         t = _lib.Tree(int(nlevels), 0, float(delta1), float(rmin))
-        call = lambda ptr, mem: lib().estimate_4pcf_multipoles_tree(*m.refs(), C.byref(t), ptr, mem)
+        check(lib().estimate_4pcf_multipoles_tree(*m.refs(), C.byref(t), C.c_void_p(ptr), mem))
     else:
-        call = lambda ptr, mem: lib().estimate_4pcf_multipoles(*m.refs(), ptr, mem)
-    if m.device:
-        import torch
-        res = out if out is not None else torch.empty(shape, dtype=torch.complex128, device=m.torch_device)
-        check(call(C.c_void_p(res.data_ptr()), MEM_DEVICE))
-        return res
-    res = out if out is not None else np.empty(shape, dtype=np.complex128)
-    check(call(C.c_void_p(res.ctypes.data), MEM_HOST))
+        check(lib().estimate_4pcf_multipoles(*m.refs(), C.c_void_p(ptr), mem))
     return res
 
 
@@ -135,14 +193,8 @@ def estimate_3pcf_multipoles(x, y, g1, g2, w, edges, nmax: int, precision="fp64"
     torch tensor on the inputs' device for device inputs).  nmax <= 32."""
     m = _Marshal(x, y, g1, g2, w, edges, nmax, precision, subtract_degenerate, centers,
                  tile_centers, stream)
-    shape = output3_shape(m.nbins, m.nmax)
-    if m.device:
-        import torch
-        res = out if out is not None else torch.empty(shape, dtype=torch.complex128, device=m.torch_device)
-        check(lib().estimate_3pcf_multipoles(*m.refs(), C.c_void_p(res.data_ptr()), MEM_DEVICE))
-        return res
-    res = out if out is not None else np.empty(shape, dtype=np.complex128)
-    check(lib().estimate_3pcf_multipoles(*m.refs(), C.c_void_p(res.ctypes.data), MEM_HOST))
+    res, ptr, mem = m.output(output3_shape(m.nbins, m.nmax), out)
+    check(lib().estimate_3pcf_multipoles(*m.refs(), C.c_void_p(ptr), mem))
     return res
 
 
@@ -170,7 +222,8 @@ def to_natural(upsilon, nphi: int, stream=None):
     gam = np.empty((8, nb, nb, nb, nphi, nphi), dtype=np.complex128)
     nrm = np.empty((nb, nb, nb, nphi, nphi), dtype=np.float64)
     check(lib().fpcf4_to_natural(C.c_void_p(u.ctypes.data), nb, nmax, int(nphi),
-                                 C.c_void_p(gam.ctypes.data), C.c_void_p(nrm.ctypes.data), stream))
+                                 C.c_void_p(gam.ctypes.data), C.c_void_p(nrm.ctypes.data),
+                                 _stream_handle(stream)))
     return gam, nrm
 
 
@@ -187,8 +240,10 @@ def to_natural_triplets(upsilon, nphi: int, triplets, stream=None):
         nb, nmax = u.shape[1], (u.shape[-1] - 1) // 2
         gam = torch.empty((8, ntrip, nphi, nphi), dtype=torch.complex128, device=u.device)
         nrm = torch.empty((ntrip, nphi, nphi), dtype=torch.float64, device=u.device)
+        stream = _stream_handle(stream)
         if stream is None:
             stream = torch.cuda.current_stream(u.device).cuda_stream
+        _order_after_current(stream, u.device)
         check(lib().fpcf4_to_natural_triplets(C.c_void_p(u.data_ptr()), MEM_DEVICE, nb, nmax, int(nphi),
                                               C.c_void_p(t.ctypes.data), ntrip, C.c_void_p(gam.data_ptr()),
                                               C.c_void_p(nrm.data_ptr()), MEM_DEVICE, stream))
@@ -199,7 +254,7 @@ def to_natural_triplets(upsilon, nphi: int, triplets, stream=None):
     nrm = np.empty((ntrip, nphi, nphi), dtype=np.float64)
     check(lib().fpcf4_to_natural_triplets(C.c_void_p(u.ctypes.data), MEM_HOST, nb, nmax, int(nphi),
                                           C.c_void_p(t.ctypes.data), ntrip, C.c_void_p(gam.ctypes.data),
-                                          C.c_void_p(nrm.ctypes.data), MEM_HOST, stream))
+                                          C.c_void_p(nrm.ctypes.data), MEM_HOST, _stream_handle(stream)))
     return gam, nrm
 
 
@@ -260,6 +315,17 @@ class Request:
         if workspace.numel() < self.bytes:
             raise Fpcf4Error(_lib.E_BUDGET, "workspace too small")
         self.workspace = workspace
+        s = self.m.stream
+        if s is not None and s != torch.cuda.current_stream(workspace.device).cuda_stream:
+            # the request's kernels run on its own stream: order them after
+            # the inputs and the workspace, and keep torch's allocator from
+            # reusing those blocks while that stream may still use them
+            ext = torch.cuda.ExternalStream(s, device=workspace.device)
+            ext.wait_stream(torch.cuda.current_stream(workspace.device))
+            workspace.record_stream(ext)
+            for a in self.m.keep:
+                if isinstance(a, torch.Tensor) and a.is_cuda:
+                    a.record_stream(ext)
         self.handle = C.c_void_p()
         check(lib().fpcf4_request_create(*self.m.refs(), C.c_void_p(workspace.data_ptr()),
                                          self.bytes, C.byref(self.handle)))

@@ -285,10 +285,12 @@ fpcf4_status request_init(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   // never written, so they must hold zeros for the slice reduction
   if (P.corr_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_cpart, 0, P.corr_bytes * CORR_SLICES, s));
   if (P.acc3_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_acc3, 0, P.acc3_bytes, s));
-  std::vector<double> e2(P.nb + 1);
+  double e2[FPCF4_NBINS_SUPPORTED + 1];
   for (int b = 0; b <= P.nb; ++b) e2[b] = bins->edges[b] * bins->edges[b];
-  HIPCHK(hipMemcpyAsync(R->ws + P.o_e2, e2.data(), e2.size() * 8, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(R->ws + P.o_edges, bins->edges, e2.size() * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(R->ws + P.o_e2, e2, (P.nb + 1) * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(R->ws + P.o_edges, bins->edges, (P.nb + 1) * 8, hipMemcpyHostToDevice, s));
+  // the copy from the stack array must complete before it goes out of scope
+  HIPCHK(hipStreamSynchronize(s));
   if (n == 0) {
     HIPCHK(hipStreamSynchronize(s));
     return FPCF4_OK;

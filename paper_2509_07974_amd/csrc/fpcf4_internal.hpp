@@ -25,6 +25,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/fpcf4.h"
 
@@ -188,6 +189,62 @@ constexpr int CORR_SLICES = 8;   // centre slices of the correction sums
 hipError_t launch_contract(const StageBArgs& sb, int precision, int ldc, const void* xg,
                            const void* xw, const unsigned* maxima, hipStream_t s);
 template <typename T> hipError_t launch_corrections(const CorrArgs& a, hipStream_t s);
+
+// Mixed-precision contraction organised by the pair of blocks at Theta_2 and
+// Theta_3 (stage_b_pairs.hip).  A work item is one unordered pair of
+// (family, conjugation, order) for the b2 and b3 factors; its row blocks are
+// the distinct left factors x A(b1) of every (mu, n2, n3) using that pair.
+constexpr int PAIR_MAX_BLK = 4;    // row blocks per item (at most 4 for the factor table)
+constexpr int PAIR_SUB = 8192;     // centres per binary32 running sum before binary64
+struct PairRow {
+  int8_t x, fam, conj, pad;        // centre factor kind (X_*), A family (F_*), A conjugated
+  int32_t order;                   // A order
+};
+struct PairItem {
+  int8_t famB, conjB, famC, conjC;
+  int32_t ordB, ordC;
+  int32_t nblk;                    // row blocks
+  int32_t row0;                    // first row of the item in the partial layout
+  int32_t pad;
+  PairRow blk[PAIR_MAX_BLK];
+};
+struct PairOut {                   // where (mu, n2, n3) is computed
+  int32_t item, blk, transposed, pad;
+};
+struct PairPlanHost {
+  std::vector<PairItem> items;     // grouped by row-block count
+  int cls_start[PAIR_MAX_BLK + 1], cls_count[PAIR_MAX_BLK + 1];
+  std::vector<PairOut> out;        // [9][2nmax+1][2nmax+1]
+  int64_t total_rows;              // sum of 2 nb nblk over items
+};
+PairPlanHost make_pair_plan(int nmax, int nb);
+int pair_slices(int64_t ncent);    // centre slices (partial regions) for a tile
+struct PairArgs {
+  const float* rec;
+  int64_t ldc;
+  const float* xg;                 // [ldc] complex w g
+  const float* xw;                 // [ldc] w
+  const unsigned* maxima;
+  const PairItem* items;
+  int32_t item0, nitems, ncent, nb, nmax;
+  double* part;                    // [slices][total_rows][nb^2]
+  int64_t total_rows;
+};
+struct PairLaunch {
+  const void* rec;
+  int64_t ldc;
+  const void* xg;
+  const void* xw;
+  const unsigned* maxima;
+  const PairItem* items;           // device copy of the plan
+  const PairOut* out;
+  int cls_start[PAIR_MAX_BLK + 1], cls_count[PAIR_MAX_BLK + 1];
+  int ncent, nb, nmax, precision;
+  double* part;
+  int64_t total_rows;
+  double* ups;                     // accumulated into
+};
+hipError_t launch_contract_pairs(const PairLaunch& pl, hipStream_t s);
 size_t corr_elems(int nb, int nmax);  // complex elements of the correction buffer
 hipError_t launch_finalize(const double* ups_raw, const double* corr, int nb, int nmax,
                            int subtract, double* out, hipStream_t s);

@@ -13,7 +13,10 @@
 //   N   w          W_n                W_{-n}             V_0
 //
 // (a slot with exponent coefficient c is G_c, or conj G_{-c} where its shear
-// is conjugated).  For distinct neighbour pairs the j = k terms, which exist
+// is conjugated).  The natural components are products of three projected
+// shears -gamma_c e^{-2 i zeta} (Sect. 2.1), so the shear components carry a
+// factor (-1)^3 that the block products above do not: the output is
+// -Upsilon_mu for mu = 0..3 (the normalisation has no shear and no sign).  For distinct neighbour pairs the j = k terms, which exist
 // only for Theta_1 = Theta_2, are removed:
 //   Upsilon'(b, b) = Upsilon(b, b) - sum_i x_i D_mu(i, b),
 // D_mu = sum_j (slot-1 weight)(slot-2 weight) e^{i (c1 + c2) phi_ij}, the
@@ -225,8 +228,10 @@ __global__ void finalize3_kernel(const double* acc, int nb, int m, int subtract,
     vr -= acc[2 * d];
     vi -= acc[2 * d + 1];
   }
-  out[2 * i] = vr;
-  out[2 * i + 1] = vi;
+  // (-1)^3 of the three projected shears (exact)
+  const double sg = mu < 4 ? -1.0 : 1.0;
+  out[2 * i] = sg * vr;
+  out[2 * i + 1] = sg * vi;
 }
 
 }  // namespace

@@ -152,3 +152,42 @@ def test_tree_invalid_arguments_rejected(prec, tree, code):
     st = lib.estimate_4pcf_multipoles_tree(C.byref(cat), C.byref(bins), C.byref(opts), C.byref(t),
                                            C.c_void_p(out.ctypes.data), _lib.MEM_HOST)
     assert st == code, lib.fpcf4_last_error()
+
+
+@pytest.mark.parametrize("bad", ["shape", "dtype", "layout", "readonly", "torch"])
+def test_out_buffer_is_validated(bad):
+    """A caller-supplied `out` must match the result exactly (shape,
+    complex128, C-contiguous, writeable, host for host inputs): the library
+    writes through a raw pointer, so anything else is rejected before the
+    call."""
+    import paper_2509_07974_amd as m
+    ensure_built()
+    x = np.zeros(3)
+    edges = [1.0, 2.0, 4.0]
+    shape = m.output_shape(2, 1)
+    if bad == "shape":
+        out = np.zeros((9, 2, 2, 2, 3, 2), complex)
+    elif bad == "dtype":
+        out = np.zeros(shape, np.complex64)
+    elif bad == "layout":
+        out = np.zeros(shape[::-1], complex).T
+    elif bad == "readonly":
+        out = np.zeros(shape, complex)
+        out.flags.writeable = False
+    else:
+        import torch
+        out = torch.zeros(shape, dtype=torch.complex128)
+    with pytest.raises(ValueError):
+        m.estimate_4pcf_multipoles(x, x, x, x, x, edges, 1, out=out)
+    with pytest.raises(ValueError):
+        m.estimate_3pcf_multipoles(x, x, x, x, x, edges, 1, out=np.zeros((5, 2, 2, 4), complex))
+
+
+@pytest.mark.gpu
+def test_valid_host_out_is_filled_in_place():
+    import paper_2509_07974_amd as m
+    ensure_built()
+    x = np.array([0.0, 100.0, 200.0])   # no pair in range: the result is zero
+    out = np.full(m.output_shape(2, 1), 7 + 7j)
+    got = m.estimate_4pcf_multipoles(x, x, x, x, x + 1, [1.0, 2.0, 4.0], 1, out=out)
+    assert got is out and not np.any(out)

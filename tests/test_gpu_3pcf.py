@@ -1,9 +1,11 @@
 """GPU parity of the shear 3PCF multipoles (the order-N construction at
 N = 3, read from the stage (a) records) against the FP64 oracle.
 
-Bars as for the 4PCF: <= 1e-10 normwise per component in the FP64 path,
-<= 1e-5 in the mixed paths (binary32 stage (a); the 3PCF contraction is
-binary64 in both).  At the full 1e6-galaxy size the oracle takes sampled
+Bars as for the 4PCF (helpers.assert_parity over all bin pairs and the
+diagonal b1 = b2 alone, where the same-neighbour terms are removed): <= 1e-10
+normwise per component in the FP64 path, <= 1e-5 in the mixed paths
+(binary32 stage (a); the 3PCF contraction is binary64 in both), with the
+largest-element, element-wise and term-scale bars.  At the full 1e6-galaxy size the oracle takes sampled
 centres; the all-centre result is checked by the Theta_1 <-> Theta_2
 relabelling relations, which hold at any size.
 """
@@ -14,7 +16,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import rel_per_mu
+from helpers import assert_parity, rel_per_mu
 
 pytestmark = pytest.mark.gpu
 
@@ -42,6 +44,12 @@ def c0_ref(distinct=True):
 
 
 @functools.lru_cache(None)
+def c0_bound():
+    cat, edges = c0()
+    return oracle.abs_bound(*cat.arrays(), edges, order=3)
+
+
+@functools.lru_cache(None)
 def small(n=400, seed=21):
     cat, _ = c0()
     idx = np.random.default_rng(seed).choice(cat.n, n, replace=False)
@@ -53,17 +61,14 @@ def test_3pcf_c0_distinct(fp, prec):
     cat, edges = c0()
     got = fp.estimate_3pcf_multipoles(*cat.arrays(), edges, M3, precision=prec)
     assert got.shape == (5, 4, 4, 2 * M3 + 1)
-    err = rel_per_mu(got, c0_ref(True))
-    print(prec, err)
-    assert np.all(err < TOL[prec]), err
+    assert_parity(got, c0_ref(True), prec, c0_bound(), nbin=2, label="3pcf c0")
 
 
 def test_3pcf_c0_raw_fp64(fp):
     cat, edges = c0()
     got = fp.estimate_3pcf_multipoles(*cat.arrays(), edges, M3, precision="fp64",
                                       subtract_degenerate=False)
-    err = rel_per_mu(got, c0_ref(False))
-    assert np.all(err < 1e-10), err
+    assert_parity(got, c0_ref(False), "fp64", c0_bound(), nbin=2, label="3pcf c0 raw")
     # the same-neighbour terms sit on the diagonal b1 == b2 only
     dist = fp.estimate_3pcf_multipoles(*cat.arrays(), edges, M3, precision="fp64")
     off = ~np.eye(4, dtype=bool)
@@ -78,19 +83,19 @@ def test_3pcf_multipole_orders(fp, m):
     _, edges = c0()
     got = fp.estimate_3pcf_multipoles(*c.arrays(), edges, m, precision="fp64")
     ref = oracle.upsilon3(*c.arrays(), edges, m)
-    err = rel_per_mu(got, ref)
-    assert np.all(err < 1e-10), (m, err)
+    S = oracle.abs_bound(*c.arrays(), edges, order=3)
+    assert_parity(got, ref, "fp64", S, nbin=2, label=f"3pcf m {m}")
 
 
 @pytest.mark.parametrize("nb", [1, 9, 16])
 def test_3pcf_bin_counts(fp, nb):
     c = small()
     edges = synth.log_edges(1.0, 30.0, nb)
-    for prec in ("fp64", "fp16"):
+    ref = oracle.upsilon3(*c.arrays(), edges, 3)
+    S = oracle.abs_bound(*c.arrays(), edges, order=3)
+    for prec in ("fp64", "fp16", "bf16"):
         got = fp.estimate_3pcf_multipoles(*c.arrays(), edges, 3, precision=prec)
-        ref = oracle.upsilon3(*c.arrays(), edges, 3)
-        err = rel_per_mu(got, ref)
-        assert np.all(err < TOL[prec]), (nb, prec, err)
+        assert_parity(got, ref, prec, S, nbin=2, label=f"3pcf nb {nb}")
 
 
 def test_3pcf_tiles_match_single_tile(fp):
@@ -105,7 +110,8 @@ def test_3pcf_centre_subset(fp):
     idx = np.random.default_rng(3).choice(cat.n, 150, replace=False)
     got = fp.estimate_3pcf_multipoles(*cat.arrays(), edges, M3, precision="fp64", centers=idx)
     ref = oracle.upsilon3(*cat.arrays(), edges, M3, centers=idx)
-    assert np.all(rel_per_mu(got, ref) < 1e-10)
+    assert_parity(got, ref, "fp64", oracle.abs_bound(*cat.arrays(), edges, idx, order=3), nbin=2,
+                  label="3pcf subset")
 
 
 def test_3pcf_empty_and_out_of_range(fp):
@@ -117,6 +123,24 @@ def test_3pcf_empty_and_out_of_range(fp):
     x = np.array([0.0, 100.0])
     got = fp.estimate_3pcf_multipoles(x, x, x * 0 + .1, x * 0, x * 0 + 1, edges, 3)
     assert not np.any(got)
+
+
+def test_3pcf_hand_example_on_gpu(fp):
+    """The three-galaxy example worked by hand from the projected shears of
+    Sect. 2.1 (tests/test_oracle3.py): centre (0, 0) w 2 gamma_c 0.1i,
+    neighbours (1.5, 0) w 1 gamma_c 0.2i and (0, 3) w 1 gamma_c 0.3i, bins
+    [1, 2), [2, 4): Gamma_0..3 = -0.012, -0.012, +0.012, +0.012 and N = 2
+    times (-i)^n at (bin 0, bin 1), i^n at (bin 1, bin 0)."""
+    x = np.array([0.0, 1.5, 0.0]); y = np.array([0.0, 0.0, 3.0])
+    g1 = np.zeros(3); g2 = np.array([0.1, 0.2, 0.3]); w = np.array([2.0, 1.0, 1.0])
+    edges = np.array([1.0, 2.0, 4.0])
+    P = [-0.012, -0.012, 0.012, 0.012, 2.0]
+    for prec, tol in (("fp64", 1e-15), ("fp16", 1e-8)):
+        u = fp.estimate_3pcf_multipoles(x, y, g1, g2, w, edges, 3, precision=prec, centers=[0])
+        for mu in range(5):
+            for n in range(-3, 4):
+                assert abs(u[mu, 0, 1, n + 3] - P[mu] * (-1j) ** n) < tol * max(1, abs(P[mu])), (prec, mu, n)
+                assert abs(u[mu, 1, 0, n + 3] - P[mu] * (1j) ** n) < tol * max(1, abs(P[mu])), (prec, mu, n)
 
 
 def test_3pcf_device_inputs_match_host(fp):
@@ -134,17 +158,22 @@ def grf1m():
     return cat, edges
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+@functools.lru_cache(None)
+def grf1m_sample():
+    cat, edges = grf1m()
+    idx = np.random.default_rng(12).choice(cat.n, 8, replace=False)
+    return idx, oracle.upsilon3(*cat.arrays(), edges, 10, centers=idx), \
+        oracle.abs_bound(*cat.arrays(), edges, idx, order=3)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16", "bf16"])
 def test_3pcf_grf1m_sampled_centres(fp, prec):
     """Full-size 1e6-galaxy GRF catalogue, 12 bins, 3PCF multipoles |n| <= 10:
     seeded centres with every galaxy as neighbour."""
     cat, edges = grf1m()
-    idx = np.random.default_rng(12).choice(cat.n, 8, replace=False)
+    idx, ref, S = grf1m_sample()
     got = fp.estimate_3pcf_multipoles(*cat.arrays(), edges, 10, precision=prec, centers=idx)
-    ref = oracle.upsilon3(*cat.arrays(), edges, 10, centers=idx)
-    err = rel_per_mu(got, ref)
-    print(prec, err)
-    assert np.all(err < TOL[prec]), err
+    assert_parity(got, ref, prec, S, nbin=2, label="3pcf grf-1m")
 
 
 def test_3pcf_grf1m_all_centres_relabelling(fp):

@@ -1,6 +1,9 @@
 """GPU parity of the tree (reduced-catalogue) approximation against its FP64
-oracle, through the C ABI (mixed paths; bar 1e-5 normwise per correlator),
-plus the limits in which it must equal the discrete estimator."""
+oracle, through the C ABI (mixed paths; normwise 1e-5 per correlator, plus
+the largest-element and element-wise bars of helpers.assert_parity, over all
+triplets and the equal-bin ones), plus the limits in which it must equal the
+discrete estimator.  The term-scale bar is not used here: the discrete
+catalogue's absolute sums do not bound the pseudo-galaxy terms."""
 import functools
 
 import numpy as np
@@ -8,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import rel_per_mu
+from helpers import assert_parity, rel_per_mu
 
 pytestmark = pytest.mark.gpu
 
@@ -40,9 +43,7 @@ def test_tree_c0_matches_oracle(fp, prec):
     cat, edges, nmax = c0()
     assert oracle.tree_levels(edges, *TREE) == [0, 0, 1, 2]
     got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision=prec, tree=TREE)
-    err = rel_per_mu(got, c0_tree_ref())
-    print(prec, err)
-    assert np.all(err < 1e-5), err
+    assert_parity(got, c0_tree_ref(), prec, label="tree c0")
     # and it is an approximation: not the discrete result
     exact = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision=prec)
     assert np.max(rel_per_mu(got, exact)) > 1e-4
@@ -53,7 +54,7 @@ def test_tree_raw_sums_match_oracle(fp):
     got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp16", tree=TREE,
                                       subtract_degenerate=False)
     ref = oracle.upsilon_tree(*cat.arrays(), edges, nmax, *TREE, distinct=False)
-    assert np.all(rel_per_mu(got, ref) < 1e-5)
+    assert_parity(got, ref, "fp16", label="tree c0 raw")
 
 
 def test_tree_tiles_match_single_tile(fp):
@@ -115,6 +116,4 @@ def test_tree_grf1m_sampled_centres(fp):
     idx = np.random.default_rng(13).choice(cat.n, 6, replace=False)
     got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp16", tree=tree, centers=idx)
     ref = oracle.upsilon_tree(*cat.arrays(), edges, nmax, *tree, centers=idx)
-    err = rel_per_mu(got, ref)
-    print(err)
-    assert np.all(err < 1e-5), err
+    assert_parity(got, ref, "fp16", label="tree grf-1m")

@@ -380,3 +380,40 @@ def test_natural_triplets_equal_slices_of_full_conversion():
     for k, (a, b, c) in enumerate(trip):
         assert np.array_equal(n[k], N[a, b, c])
         assert np.array_equal(g[:, k], G[:, a, b, c])
+
+
+def test_abs_bound_bounds_every_element_and_is_exact_for_n_at_zero_multipole():
+    """The per-element scale S of the oracle (sum of absolute term values)
+    bounds |Upsilon| for raw and distinct sums alike (triangle inequality);
+    with positive weights the raw N at (n2, n3) = (0, 0) equals S[1] exactly,
+    since W_0 is then the plain weight sum of the bin."""
+    cat = synth.uniform_catalogue(9, 240, 25.0)
+    edges = synth.log_edges(1.0, 12.0, 3)
+    x, y, g1, g2, w = cat.arrays()
+    S = oracle.abs_bound(x, y, g1, g2, w, edges)
+    for distinct in (False, True):
+        u = oracle.upsilon(x, y, g1, g2, w, edges, 2, distinct=distinct)
+        assert np.all(np.abs(u[:8]) <= S[0][None, ..., None, None] * (1 + 1e-12))
+        assert np.all(np.abs(u[8]) <= S[1][..., None, None] * (1 + 1e-12))
+    raw = oracle.upsilon(x, y, g1, g2, w, edges, 2, distinct=False)
+    assert np.allclose(raw[8, :, :, :, 2, 2].real, S[1], rtol=1e-13, atol=0)
+    # the 3PCF variant bounds the order-3 sums the same way
+    S3 = oracle.abs_bound(x, y, g1, g2, w, edges, order=3)
+    u3 = oracle.upsilon3(x, y, g1, g2, w, edges, 2, distinct=False)
+    assert np.all(np.abs(u3[:4]) <= S3[0][None, ..., None] * (1 + 1e-12))
+    assert np.allclose(u3[4, :, :, 2].real, S3[1], rtol=1e-13, atol=0)
+
+
+def test_parallel_oracle_equals_serial():
+    """The process-pool variants (used to time the CPU baseline and for the
+    large sampled parity cases) add chunk results in chunk order: equal to the
+    serial oracle up to the order of the additions."""
+    cat = synth.uniform_catalogue(10, 300, 30.0)
+    edges = synth.log_edges(1.0, 15.0, 3)
+    idx = np.arange(0, 300, 3)
+    ser = oracle.upsilon(*cat.arrays(), edges, 2, centers=idx)
+    par = oracle.upsilon_parallel(*cat.arrays(), edges, 2, centers=idx, processes=3, parts=5)
+    assert np.allclose(par, ser, rtol=1e-13, atol=1e-13 * np.abs(ser).max())
+    sb = oracle.abs_bound(*cat.arrays(), edges, idx)
+    pb = oracle.abs_bound_parallel(*cat.arrays(), edges, idx, processes=3)
+    assert np.allclose(pb, sb, rtol=1e-13, atol=0)

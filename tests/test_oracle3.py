@@ -150,3 +150,31 @@ def test_planted_mistakes_are_caught():
     for bad in (sign_flip, no_factor_two, swapped):
         got = oracle.upsilon3(*cat, EDGES, 3, coeff=bad)
         assert np.any(rel(got[:4], ref[:4]) > 1e-3), bad.__name__
+
+
+def test_hand_example_three_galaxies():
+    """Worked by hand from the definitions, not by the oracle: centre i at the
+    origin (w 2, gamma_c = 0.1i), neighbour j at (1.5, 0) (w 1, gamma_c =
+    0.2i, phi = 0, bin [1, 2)), neighbour k at (0, 3) (w 1, gamma_c = 0.3i,
+    phi = pi/2, bin [2, 4)).  For (Theta_1, Theta_2) = (bin 0, bin 1):
+    zeta_0 = pi/4, zeta_1 = 0, zeta_2 = pi/2, and the projected shears
+    -gamma_c e^{-2i zeta} (Sect. 2.1) are -0.1, -0.2i and +0.3i, so
+      Gamma_0 = (-0.1)(-0.2i)(0.3i) = -0.006,  Gamma_1 (centre conjugated)
+      = -0.006,  Gamma_2 (slot 1) = (-0.1)(0.2i)(0.3i) = +0.006,
+      Gamma_3 (slot 2) = (-0.1)(-0.2i)(-0.3i) = +0.006,
+    times w_i w_j w_k = 2 and e^{-i n phi_12}, phi_12 = pi/2: (-i)^n.  For
+    (bin 1, bin 0) the slots swap: phi_12 = -pi/2, the same products, i^n.
+    A sign convention without the minus of the projection flips every shear
+    component here."""
+    x = np.array([0.0, 1.5, 0.0]); y = np.array([0.0, 0.0, 3.0])
+    g1 = np.zeros(3); g2 = np.array([0.1, 0.2, 0.3]); w = np.array([2.0, 1.0, 1.0])
+    edges = np.array([1.0, 2.0, 4.0])
+    P = [-0.012, -0.012, 0.012, 0.012, 2.0]
+    for fn in (lambda: nth.upsilon3(x, y, g1, g2, w, edges, 3, centers=[0]),
+               lambda: nth.brute_upsilon3(x, y, g1, g2, w, edges, 3, centers=[0])):
+        u = fn()
+        for mu in range(5):
+            for n in range(-3, 4):
+                assert abs(u[mu, 0, 1, n + 3] - P[mu] * (-1j) ** n) < 1e-15
+                assert abs(u[mu, 1, 0, n + 3] - P[mu] * (1j) ** n) < 1e-15
+                assert abs(u[mu, 0, 0, n + 3]) < 1e-15 and abs(u[mu, 1, 1, n + 3]) < 1e-15
