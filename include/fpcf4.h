@@ -121,6 +121,26 @@ fpcf4_status estimate_4pcf_multipoles(const fpcf4_catalogue *cat,
                                       const fpcf4_options *opts,
                                       double *upsilon, int32_t out_mem);
 
+/* Bytes of the static device scratch of estimate_4pcf_multipoles_noalloc. */
+#define FPCF4_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* estimate_4pcf_multipoles for callers that cannot allocate device memory
+ * (serving loops that must not call hipMalloc, harnesses that forbid it):
+ * same arguments, output and errors, but the workspace is a static device
+ * array of FPCF4_NOALLOC_SCRATCH_BYTES (64 MiB) that each GPU the library
+ * runs on holds until the process ends; no device memory is allocated or
+ * freed.  With opts->tile_centers == 0 the centre tile is halved until the
+ * workspace fits; a workspace that still does not fit (or does not fit at
+ * the caller's tile) fails with FPCF4_E_BUDGET before any device work.
+ * Every call on one GPU uses the same array, and each call re-initialises
+ * what must start at zero: calls are serialised within this process, and
+ * calls from other processes on the same GPU race and must not overlap.
+ * The call waits for `stream` before returning. */
+fpcf4_status estimate_4pcf_multipoles_noalloc(const fpcf4_catalogue *cat,
+                                              const fpcf4_bins *bins,
+                                              const fpcf4_options *opts,
+                                              double *upsilon, int32_t out_mem);
+
 /* Number of complex128 elements of the 3PCF output: 5 * nbins^2 * (2 nmax + 1). */
 int64_t fpcf4_output3_elems(int32_t nbins, int32_t nmax);
 

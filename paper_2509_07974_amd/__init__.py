@@ -13,14 +13,15 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (FP64, MIXED_FP16, MIXED_BF16, MEM_HOST, MEM_DEVICE, NMAX_SUPPORTED,
+from ._lib import (FP64, MIXED_FP16, MIXED_BF16, MEM_HOST, MEM_DEVICE, NMAX_SUPPORTED, NOALLOC_SCRATCH_BYTES,
                    NBINS_SUPPORTED, Fpcf4Error, check, lib)
 
-__all__ = ["estimate_4pcf_multipoles", "estimate_3pcf_multipoles",
+__all__ = ["estimate_4pcf_multipoles", "estimate_4pcf_multipoles_noalloc", "estimate_3pcf_multipoles",
            "debug_multipoles", "to_natural",
            "to_natural_triplets", "natural_blocks", "plan", "Request",
            "profile_enable", "profile_read",
-           "PRECISIONS", "Fpcf4Error", "output_shape", "output3_shape", "lib", "version"]
+           "PRECISIONS", "Fpcf4Error", "output_shape", "output3_shape", "lib", "version",
+           "NOALLOC_SCRATCH_BYTES"]
 
 PRECISIONS = {"fp64": FP64, "fp16": MIXED_FP16, "bf16": MIXED_BF16}
 
@@ -182,6 +183,21 @@ def estimate_4pcf_multipoles(x, y, g1, g2, w, edges, nmax: int, precision="fp64"
         check(lib().estimate_4pcf_multipoles_tree(*m.refs(), C.byref(t), C.c_void_p(ptr), mem))
     else:
         check(lib().estimate_4pcf_multipoles(*m.refs(), C.c_void_p(ptr), mem))
+    return res
+
+
+def estimate_4pcf_multipoles_noalloc(x, y, g1, g2, w, edges, nmax: int, precision="fp64",
+                                     subtract_degenerate: bool = True, centers=None,
+                                     tile_centers: int = 0, stream=None, out=None):
+    """estimate_4pcf_multipoles with the library's static device scratch
+    (NOALLOC_SCRATCH_BYTES) as workspace: the library allocates no device
+    memory.  Workloads whose workspace does not fit raise Fpcf4Error
+    (E_BUDGET).  Pass `out` to keep the call free of allocations on the
+    Python side as well."""
+    m = _Marshal(x, y, g1, g2, w, edges, nmax, precision, subtract_degenerate, centers,
+                 tile_centers, stream)
+    res, ptr, mem = m.output(output_shape(m.nbins, m.nmax), out)
+    check(lib().estimate_4pcf_multipoles_noalloc(*m.refs(), C.c_void_p(ptr), mem))
     return res
 
 

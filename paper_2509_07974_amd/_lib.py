@@ -13,6 +13,7 @@ FP64, MIXED_FP16, MIXED_BF16 = 0, 1, 2
 NMAX_SUPPORTED = 16
 NMAX3_SUPPORTED = 32
 NBINS_SUPPORTED = 16
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 STATUS_NAMES = {
     OK: "OK", E_INVALID_ARG: "E_INVALID_ARG", E_UNSUPPORTED: "E_UNSUPPORTED",
@@ -112,6 +113,8 @@ def lib():
     L.estimate_4pcf_multipoles_tree.argtypes = [P(Catalogue), P(Bins), P(Options), P(Tree), C.c_void_p,
                                                 C.c_int32]
     L.estimate_4pcf_multipoles_tree.restype = C.c_int32
+    L.estimate_4pcf_multipoles_noalloc.argtypes = [P(Catalogue), P(Bins), P(Options), C.c_void_p, C.c_int32]
+    L.estimate_4pcf_multipoles_noalloc.restype = C.c_int32
     _lib = L
     return L
 
@@ -126,5 +129,5 @@ EXPORTED = [
     "fpcf4_request_create", "fpcf4_request_step", "fpcf4_request_finalize",
     "fpcf4_request_destroy", "fpcf4_last_error", "fpcf4_version", "fpcf4_output_elems",
     "fpcf4_profile_enable", "fpcf4_profile_read", "estimate_3pcf_multipoles", "fpcf4_output3_elems",
-    "fpcf4_to_natural_triplets", "estimate_4pcf_multipoles_tree",
+    "fpcf4_to_natural_triplets", "estimate_4pcf_multipoles_tree", "estimate_4pcf_multipoles_noalloc",
 ]

@@ -230,7 +230,17 @@ __global__ void zero_kernel(int32_t* p, int n) {
   if (i < n) p[i] = 0;
 }
 
+// Device address of the static scratch array of the allocation-free entry
+// point, looked up once per device (the array's host-side name is only a
+// stand-in for the symbol, never a device address).
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
 }  // namespace
+
+// Workspace of estimate_4pcf_multipoles_noalloc: one copy per device, held
+// until the process ends.  Every call on a device shares it.
+static __device__ __align__(256) unsigned char scratch[FPCF4_NOALLOC_SCRATCH_BYTES];
 
 struct fpcf4_request {
   PlanInfo P;
@@ -239,6 +249,7 @@ struct fpcf4_request {
   Grid grid{};
   std::vector<char> stepped;
   bool want_counts = false;
+  bool no_events = false;       // allocation-free path: never create profiling events
   std::vector<hipEvent_t> ev;   // 4 per profiled step
   int64_t prof_a_launches = 0, prof_b_launches = 0, prof_steps = 0, prof_centres = 0;
   ~fpcf4_request() {
@@ -381,7 +392,7 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
   bool prof;
   {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    prof = g_prof_on && stage_b;
+    prof = g_prof_on && stage_b && !R->no_events;
   }
   hipEvent_t evs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   if (prof) {
@@ -594,6 +605,45 @@ fpcf4_status estimate_4pcf_multipoles(const fpcf4_catalogue* cat, const fpcf4_bi
   fpcf4_request_destroy(R);
   hipError_t e = hipFreeAsync(ws, s);
   if (st == FPCF4_OK && e != hipSuccess) return fail(FPCF4_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));
+  return st;
+}
+
+fpcf4_status estimate_4pcf_multipoles_noalloc(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
+                                              const fpcf4_options* opts, double* upsilon, int32_t out_mem) {
+  if (!upsilon) return fail(FPCF4_E_INVALID_ARG, "null output");
+  if (out_mem != FPCF4_MEM_HOST && out_mem != FPCF4_MEM_DEVICE) return fail(FPCF4_E_INVALID_ARG, "out_mem %d", out_mem);
+  PlanInfo P;
+  fpcf4_status st = make_plan(cat, bins, opts, P);
+  if (st != FPCF4_OK) return st;
+  fpcf4_options o = *opts;
+  if (P.total > FPCF4_NOALLOC_SCRATCH_BYTES && opts->tile_centers == 0) {
+    // smaller centre tiles shrink the per-tile record buffers
+    for (int64_t tile = P.tile / 2; tile >= 64 && P.total > FPCF4_NOALLOC_SCRATCH_BYTES; tile /= 2) {
+      o.tile_centers = tile;
+      if ((st = make_plan(cat, bins, &o, P)) != FPCF4_OK) return st;
+    }
+  }
+  if (P.total > FPCF4_NOALLOC_SCRATCH_BYTES)
+    return fail(FPCF4_E_BUDGET, "workspace of %zu bytes exceeds the static scratch of %zu bytes", P.total,
+                (size_t)FPCF4_NOALLOC_SCRATCH_BYTES);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(FPCF4_E_UNSUPPORTED, "device index %d", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);   // one call at a time in this process
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(FPCF4_E_DEVICE, "no device address for the static scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  fpcf4_request R;
+  R.no_events = true;
+  st = request_init(cat, bins, &o, g_scratch_ptr[dev], FPCF4_NOALLOC_SCRATCH_BYTES, &R);
+  for (int64_t t = 0; st == FPCF4_OK && t < R.P.ntiles; ++t) st = request_step(&R, t, true);
+  if (st == FPCF4_OK) st = fpcf4_request_finalize(&R, upsilon, out_mem);
+  // leave the scratch idle for the next call even after an error
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(o.stream));
+  if (st == FPCF4_OK && e != hipSuccess) return fail(FPCF4_E_DEVICE, "sync: %s", hipGetErrorString(e));
   return st;
 }
 

@@ -154,6 +154,27 @@ def test_tree_invalid_arguments_rejected(prec, tree, code):
     assert st == code, lib.fpcf4_last_error()
 
 
+def test_noalloc_rejects_oversized_workspace_before_device_work():
+    """The allocation-free entry point checks the planned workspace against
+    its static scratch on the host: a catalogue of 2e6 galaxies needs more
+    than 64 MiB at any centre tile (galaxy records and cell list alone), so
+    the call fails with E_BUDGET before any device work (no GPU here)."""
+    from paper_2509_07974_amd import _lib
+    lib = ensure_built()
+    z = np.zeros(1)
+    e = np.array([1.0, 2.0, 4.0])
+    cat = _lib.Catalogue(2_000_000, *[z.ctypes.data] * 5, _lib.MEM_HOST)
+    bins = _lib.Bins(2, e.ctypes.data)
+    opts = _lib.Options(2, _lib.MIXED_FP16, 1, 0, None, 0, 0, None)
+    out = np.zeros(9 * 8 * 25, complex)
+    st = lib.estimate_4pcf_multipoles_noalloc(C.byref(cat), C.byref(bins), C.byref(opts),
+                                              C.c_void_p(out.ctypes.data), _lib.MEM_HOST)
+    assert st == _lib.E_BUDGET
+    assert "static scratch" in lib.fpcf4_last_error().decode()
+    st = lib.estimate_4pcf_multipoles_noalloc(C.byref(cat), C.byref(bins), C.byref(opts), None, _lib.MEM_HOST)
+    assert st == _lib.E_INVALID_ARG
+
+
 @pytest.mark.parametrize("bad", ["shape", "dtype", "layout", "readonly", "torch"])
 def test_out_buffer_is_validated(bad):
     """A caller-supplied `out` must match the result exactly (shape,
@@ -177,8 +198,9 @@ def test_out_buffer_is_validated(bad):
     else:
         import torch
         out = torch.zeros(shape, dtype=torch.complex128)
-    with pytest.raises(ValueError):
-        m.estimate_4pcf_multipoles(x, x, x, x, x, edges, 1, out=out)
+    for f in (m.estimate_4pcf_multipoles, m.estimate_4pcf_multipoles_noalloc):
+        with pytest.raises(ValueError):
+            f(x, x, x, x, x, edges, 1, out=out)
     with pytest.raises(ValueError):
         m.estimate_3pcf_multipoles(x, x, x, x, x, edges, 1, out=np.zeros((5, 2, 2, 4), complex))
 
