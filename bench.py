@@ -134,48 +134,62 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Mock request stream for the latency report: the first SERVE_REQUESTS
-# requests of the seeded stream (N log-uniform in [1e5, 2e6] scaled by
-# SERVE_N_SCALE, square patches of 4-100 deg^2, 8-16 log bins over 1-100',
-# nmax 8), Poisson arrivals at a fixed rate.  The rate is about 0.7 of the
-# service rate of these requests served one at a time (mean alone service
-# time 0.31 s on one MI355X), fixed so that latencies stay comparable between
-# builds; None derives it from the alone pass of the run itself.
-SERVE_REQUESTS = 48
-SERVE_N_SCALE = 0.25
+# Request stream for the latency report: the first SERVE_REQUESTS requests of
+# the seeded serving stream at their full size (N log-uniform in [1e5, 2e6]
+# galaxies, square patches of 4-100 deg^2, the grf-1m GRF recipe on a 4096^2
+# grid with each request's own seed, 8-16 log bins over 1-100', nmax 8),
+# arriving Poisson at a fixed rate.  The rate was calibrated once as 0.7 of
+# the alone service rate of these requests (mean alone service time 1.268 s
+# on one MI355X, `--serving-only --serve-alone`) and is frozen here so that
+# latencies stay comparable between builds.
+SERVE_REQUESTS = 32
+SERVE_N_SCALE = 1.0
+SERVE_NGRID = 4096
 SERVE_SEED = 77
-SERVE_LAMBDA = 2.25      # requests/s
+SERVE_LAMBDA = 0.55      # requests/s
+
+
+def _make_catalogues(reqs):
+    """The request catalogues, drawn in a process pool over the host's share
+    of cores (each request's GRF needs a 4096^2 FFT)."""
+    import multiprocessing as mp
+    import synth
+    procs = max(1, min(16, os.cpu_count() or 1, len(reqs)))
+    if procs == 1:
+        return [synth.make_request_catalogue(r) for r in reqs]
+    with mp.get_context("fork").Pool(procs) as pool:
+        return pool.map(synth.make_request_catalogue, reqs)
 
 
 def serving_report(precision: str, nreq: int = SERVE_REQUESTS, n_scale: float = SERVE_N_SCALE,
-                   lam_fixed=SERVE_LAMBDA):
-    import paper_2509_07974_amd as fp
+                   lam_fixed=SERVE_LAMBDA, alone: bool = False, ngrid: int = SERVE_NGRID):
+    """Latency of the request stream served with continuous batching.  With
+    `alone`, every request is first served by itself (the calibration of the
+    arrival rate, and the check that each result in the mix equals its result
+    alone, which the serving tests also assert)."""
+    import paper_2509_07974_amd as fp  # noqa: F401
     from paper_2509_07974_amd.serve import Job, Server, latency_stats
     import synth
     t = time.perf_counter()
-    reqs = synth.serving_requests(nreq, n_scale=n_scale)
-    cats = []
-    for k, r in enumerate(reqs):
-        cats.append(synth.make_request_catalogue(r))
-        if (k + 1) % 32 == 0:
-            log(f"serving: generated {k + 1} request catalogues")
+    reqs = synth.serving_requests(nreq, n_scale=n_scale, ngrid=ngrid)
+    cats = _make_catalogues(reqs)
     log(f"serving: generated {len(reqs)} request catalogues in {time.perf_counter() - t:.1f} s")
 
     def jobs():
         return [Job(r["rid"], *c.arrays(), synth.log_edges(1.0, 100.0, r["nbins"]), r["nmax"],
                     precision=precision) for r, c in zip(reqs, cats)]
 
-    alone = jobs()
     service = []
-    for k, j in enumerate(alone):
-        srv = Server()
-        t = time.perf_counter()
-        srv.submit(j)
-        srv.drain()
-        service.append(time.perf_counter() - t)
-        if (k + 1) % 16 == 0:
-            log(f"serving: alone pass {k + 1}/{len(alone)} requests, {sum(service):.1f} s")
-    log(f"serving: alone pass {sum(service):.1f} s")
+    if alone:
+        single = jobs()
+        for k, j in enumerate(single):
+            srv = Server()
+            t = time.perf_counter()
+            srv.submit(j)
+            srv.drain()
+            service.append(time.perf_counter() - t)
+            if (k + 1) % 8 == 0:
+                log(f"serving: alone pass {k + 1}/{len(single)} requests, {sum(service):.1f} s")
     lam = lam_fixed if lam_fixed else 0.7 / float(np.mean(service))
     rng = np.random.default_rng(SERVE_SEED)
     arrivals = np.cumsum(rng.exponential(1.0 / lam, len(reqs)))
@@ -201,33 +215,62 @@ def serving_report(precision: str, nreq: int = SERVE_REQUESTS, n_scale: float = 
             log(f"serving: mix pass {len(srv.finished)}/{len(mix)} finished")
     wall = time.perf_counter() - t
     stats = latency_stats(mix)
-    equal = all(m.state == "done" and a.state == "done" and np.array_equal(m.result, a.result)
-                for m, a in zip(mix, alone))
     centres = sum(j.n for j in mix if j.state == "done")
     log(f"serving: mix pass {wall:.1f} s, p50 {stats['p50_s']:.3f} s, p99 {stats['p99_s']:.3f} s")
-    return {"requests": len(mix), "precision": precision, "lambda_per_s": lam,
-            "lambda_source": "fixed" if lam_fixed else "0.7 / mean alone service time",
-            "p50_latency_s": stats["p50_s"], "p99_latency_s": stats["p99_s"],
-            "mean_latency_s": stats["mean_s"], "max_latency_s": stats["max_s"],
-            "service_alone_p50_s": float(np.median(service)), "service_alone_mean_s": float(np.mean(service)),
-            "wall_s": wall, "centres_per_s": centres / wall,
-            "hbm_budget_bytes": srv.budget, "peak_admitted_bytes": srv.peak_used,
-            "mix_equals_alone": bool(equal),
-            "stream": f"seeded requests 0..{len(mix) - 1} (seeds 1000+r), N scaled by {n_scale}, "
-                      f"Poisson arrivals seed {SERVE_SEED}"}
+    rep = {"requests": len(mix), "precision": precision, "lambda_per_s": lam,
+           "lambda_source": "fixed (0.7 / mean alone service time, calibrated once)" if lam_fixed
+           else "0.7 / mean alone service time of this run",
+           "p50_latency_s": stats["p50_s"], "p99_latency_s": stats["p99_s"],
+           "mean_latency_s": stats["mean_s"], "max_latency_s": stats["max_s"],
+           "wall_s": wall, "centres_per_s": centres / wall, "galaxies": int(sum(r["n"] for r in reqs)),
+           "all_done": all(j.state == "done" for j in mix),
+           "hbm_budget_bytes": srv.budget, "peak_admitted_bytes": srv.peak_used,
+           "stream": f"seeded requests 0..{len(mix) - 1} (seeds 1000+r) at N x {n_scale:g}, GRF on a "
+                     f"{ngrid}^2 grid, Poisson arrivals seed {SERVE_SEED}"}
+    if alone:
+        rep.update({"service_alone_p50_s": float(np.median(service)),
+                    "service_alone_mean_s": float(np.mean(service)),
+                    "mix_equals_alone": bool(all(m.state == "done" and a.state == "done"
+                                                 and np.array_equal(m.result, a.result)
+                                                 for m, a in zip(mix, single)))})
+    return rep
 
 
-def stage_b_roofline(ncent, nb, nmax, precision, ms):
+def c4_report(precision: str):
+    """One timed estimate of the largest workload: 2400'x2400', 1e7 galaxies
+    on a lognormal density, 16 log bins 0.5-200', nmax 15, centre tiles
+    chosen by the planner (catalogue already on the device)."""
+    import torch
+    import paper_2509_07974_amd as fp
+    import synth
+    t = time.perf_counter()
+    cat, edges, nmax, desc = synth.workload("lognormal-10m")
+    gen = time.perf_counter() - t
+    log(f"lognormal-10m: generated in {gen:.1f} s")
+    dev = [torch.from_numpy(a).cuda() for a in cat.arrays()]
+    torch.cuda.synchronize()
+    fp.profile_enable(True)
+    t = time.perf_counter()
+    out = fp.estimate_4pcf_multipoles(*dev, edges, nmax, precision=precision)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    prof = fp.profile_read()
+    fp.profile_enable(False)
+    del out, dev
+    log(f"lognormal-10m: {dt:.2f} s per estimate")
+    return {"workload": "lognormal-10m", "description": desc, "precision": precision, "value": cat.n / dt,
+            "unit": "centres/s", "seconds": dt, "tiles": prof["steps"],
+            "stage_ms": {k: prof[k + "_ms"] for k in ("stage_a", "relayout", "stage_b", "corr")},
+            "generation_s": gen}
+
+
+def stage_b_roofline(ncent, nb, nmax, precision, ms, issued):
     """MFMA roofline of the contraction: useful flops (8 per complex
-    multiply-add, 9 nb^3 (2nmax+1)^2 per centre) and issued flops (rows of
-    each correlator group padded to 16, K split into real and imaginary
-    parts, x3 for the hi/lo products of the 16-bit paths), over the measured
-    stage time."""
+    multiply-add, 9 nb^3 (2nmax+1)^2 per centre) and the matrix-core flops
+    the library reports it issued (padding, surplus tiles and the three hi/lo
+    products of the 16-bit paths included), over the measured stage time."""
     nn = 2 * nmax + 1
     useful = 8.0 * 9 * nb ** 3 * nn * nn * ncent
-    rows = [2 * 2 * nb] * 2 + [2 * nb] * 5           # groups {0,3}, {1,6} and five single ones
-    rows = [(r + 15) // 16 * 16 for r in rows]
-    issued = sum(rows) * nb * nb * 2 * 2 * nn * nn * ncent * (1 if precision == "fp64" else 3)
     peak = PEAK_FP64_MFMA if precision == "fp64" else PEAK_F16_MFMA
     t = ms * 1e-3
     return {"bound": "mfma", "useful_tflops": useful / t / 1e12, "issued_tflops": issued / t / 1e12,
@@ -349,6 +392,9 @@ def main():
     ap.add_argument("--serve-n-scale", type=float, default=SERVE_N_SCALE)
     ap.add_argument("--serve-lambda", type=float, default=SERVE_LAMBDA or 0.0,
                     help="arrival rate (requests/s); 0 = 0.7 / mean alone service time")
+    ap.add_argument("--serve-alone", action="store_true",
+                    help="serve every request alone first (calibrates the rate, checks mix == alone)")
+    ap.add_argument("--no-c4", action="store_true", help="skip the timed lognormal-10m estimate")
     ap.add_argument("--no-3pcf", action="store_true", help="skip the 3PCF run on the same catalogue")
     ap.add_argument("--no-tree", action="store_true", help="skip the tree-approximation run")
     ap.add_argument("--no-natural", action="store_true",
@@ -365,7 +411,8 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.serving_only:
-        rep = serving_report(args.precision, args.serve_requests, args.serve_n_scale, args.serve_lambda or None)
+        rep = serving_report(args.precision, args.serve_requests, args.serve_n_scale, args.serve_lambda or None,
+                             alone=args.serve_alone)
         print(json.dumps({"serving": rep}))
         return
 
@@ -422,7 +469,8 @@ def main():
     extra = {"stage_ms_per_step": {k: prof[k + "_ms"] / steps for k in ("stage_a", "relayout", "stage_b", "corr")},
              "generation_s": gen_s,
              "roofline_stage_b": stage_b_roofline(cat.n, len(edges) - 1, nmax, args.precision,
-                                                  prof["stage_b_ms"] / steps)}
+                                                  prof["stage_b_ms"] / steps,
+                                                  prof["stage_b_mfma_flops"] / steps)}
     log(f"timed {args.steps} steps: {dt:.3f} s/step")
     if not args.no_fp64 and args.precision != "fp64":
         ref = run("fp64")
@@ -473,11 +521,16 @@ def main():
                        "nbins": len(edges) - 1, "nmax": nmax, "precision": args.precision},
             "roofline": roof}
     if not args.no_serving:
-        extra["serving"] = serving_report(args.precision, args.serve_requests, args.serve_n_scale,
-                                          args.serve_lambda or None)
-        line["latency"] = {"p50_s": extra["serving"]["p50_latency_s"],
-                           "p99_s": extra["serving"]["p99_latency_s"],
-                           "workload": "mock request stream, see extra.serving"}
+        sv = serving_report(args.precision, args.serve_requests, args.serve_n_scale,
+                            args.serve_lambda or None, alone=args.serve_alone)
+        extra["serving"] = sv
+        line["latency"] = {"p50_s": sv["p50_latency_s"], "p99_s": sv["p99_latency_s"],
+                           "workload": f"first {sv['requests']} requests of the seeded serving stream at "
+                                       f"full N ({sv['galaxies']} galaxies in all, 1e5-2e6 each, GRF on a "
+                                       f"{SERVE_NGRID}^2 grid, 8-16 bins, nmax 8), Poisson arrivals at "
+                                       f"{sv['lambda_per_s']:g}/s"}
+    if not args.no_c4:
+        extra["lognormal_10m"] = c4_report(args.precision)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         line["cpu_baseline"] = cpu_baseline(cat, edges, nmax)

@@ -294,6 +294,8 @@ typedef struct {
   double stage_b_ms;    /* contraction                                   */
   double corr_ms;       /* degenerate-term sums                          */
   int64_t stage_a_launches, stage_b_launches, steps, pairs, centres;
+  double stage_b_mfma_flops;  /* matrix-core flops the contraction issued
+                                 (padding and hi/lo products included)    */
 } fpcf4_profile;
 
 /* Enable (on != 0) or disable timing; either call resets the totals. */

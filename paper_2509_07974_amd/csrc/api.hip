@@ -70,7 +70,10 @@ struct PlanInfo {
   // persistent buffers
   size_t o_gal, o_cells, o_centres, o_e2, o_edges, o_counters, o_bbox, o_bad,
       o_pairs, o_part, o_ups, o_bpart, o_yprep, o_corr, o_cpart, o_acc3, o_part3, o_xg, o_xw, o_counts,
-      o_aos, o_region;
+      o_aos, o_region, o_pitems, o_pout, o_ppart;
+  // mixed-precision contraction by Theta_2/Theta_3 block pairs
+  int pslices = 0;
+  int64_t pitems = 0, prows = 0;
   int bslices = 1;             // centre slices of the contraction (partials when > 1)
   // tree approximation
   int tree_levels = 0;                      // grids in use (highest level of any bin)
@@ -176,9 +179,22 @@ fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   P.corr_bytes = order == 4 ? corr_elems(P.nb, P.nmax) * 16 : 0;
   P.acc3_bytes = order == 3 ? three_elems(P.nb, m3) * 16 : 0;
   P.o_ups = take(P.ups_bytes);
-  P.bslices = order == 4 ? contract_slices((int)std::min<int64_t>(P.tile, INT32_MAX), P.nmax) : 1;
+  const bool pairs = order == 4 && P.precision != FPCF4_FP64;
+  P.bslices = order == 4 && !pairs ? contract_slices((int)std::min<int64_t>(P.tile, INT32_MAX), P.nmax) : 1;
   P.o_bpart = take(P.bslices > 1 ? P.ups_bytes * P.bslices : 0);
-  P.o_yprep = take(order == 4 && P.precision != FPCF4_FP64 ? yprep_bytes(P.nb, P.nmax, P.tile) : 0);
+  P.o_yprep = take(0);
+  if (pairs) {
+    const PairPlanHost pp = make_pair_plan(P.nmax, P.nb);
+    for (const PairOut& o : pp.out)
+      if (o.item < 0 || o.item >= (int32_t)pp.items.size())
+        return fail(FPCF4_E_DEVICE, "internal: contraction plan leaves an output unassigned");
+    P.pitems = (int64_t)pp.items.size();
+    P.prows = pp.total_rows;
+    P.pslices = pair_slices(P.tile);
+  }
+  P.o_pitems = take((size_t)P.pitems * sizeof(PairItem));
+  P.o_pout = take(pairs ? (size_t)FPCF4_NCORR * nn * nn * sizeof(PairOut) : 0);
+  P.o_ppart = take((size_t)P.pslices * P.prows * P.nb * P.nb * 8);
   P.o_corr = take(P.corr_bytes);
   P.o_cpart = take(P.corr_bytes * CORR_SLICES);
   P.o_acc3 = take(P.acc3_bytes);
@@ -248,10 +264,12 @@ struct fpcf4_request {
   char* ws = nullptr;
   Grid grid{};
   std::vector<char> stepped;
+  PairPlanHost pplan;           // the pair plan uploaded into the workspace (mixed 4PCF)
   bool want_counts = false;
   bool no_events = false;       // allocation-free path: never create profiling events
   std::vector<hipEvent_t> ev;   // 4 per profiled step
   int64_t prof_a_launches = 0, prof_b_launches = 0, prof_steps = 0, prof_centres = 0;
+  double prof_b_flops = 0.0;
   ~fpcf4_request() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
@@ -289,6 +307,13 @@ fpcf4_status request_init(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
       if (hc[k] < 0 || hc[k] >= n) return fail(FPCF4_E_INVALID_ARG, "centre index %lld out of range", (long long)hc[k]);
   }
 
+  if (P.pitems > 0) {
+    R->pplan = make_pair_plan(P.nmax, P.nb);
+    HIPCHK(hipMemcpyAsync(R->ws + P.o_pitems, R->pplan.items.data(), R->pplan.items.size() * sizeof(PairItem),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(R->ws + P.o_pout, R->pplan.out.data(), R->pplan.out.size() * sizeof(PairOut),
+                          hipMemcpyHostToDevice, s));
+  }
   HIPCHK(hipMemsetAsync(R->ws + P.o_pairs, 0, 16, s));
   if (P.ups_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_ups, 0, P.ups_bytes, s));
   if (P.corr_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_corr, 0, P.corr_bytes, s));
@@ -454,8 +479,31 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
     b.ups = R->at<double>(P.o_ups);
     b.corr = R->at<double>(P.o_corr);
     b.part = P.bslices > 1 ? R->at<double>(P.o_bpart) : nullptr;
-    b.yprep = P.precision != FPCF4_FP64 ? R->at<double>(P.o_yprep) : nullptr;
-    HIPCHK(launch_contract(b, P.precision, (int)P.ldc, a.xg, a.xw, a.maxima, s));
+    b.yprep = nullptr;
+    if (P.pitems == 0) {
+      HIPCHK(launch_contract(b, P.precision, (int)P.ldc, a.xg, a.xw, a.maxima, s));
+    } else {
+      PairLaunch pl{};
+      pl.rec = a.rec;
+      pl.ldc = P.ldc;
+      pl.xg = a.xg;
+      pl.xw = a.xw;
+      pl.maxima = a.maxima;
+      pl.items = R->at<PairItem>(P.o_pitems);
+      pl.out = R->at<PairOut>(P.o_pout);
+      for (int c = 0; c <= PAIR_MAX_BLK; ++c) {
+        pl.cls_start[c] = R->pplan.cls_start[c];
+        pl.cls_count[c] = R->pplan.cls_count[c];
+      }
+      pl.ncent = ncent;
+      pl.nb = P.nb;
+      pl.nmax = P.nmax;
+      pl.precision = P.precision;
+      pl.part = R->at<double>(P.o_ppart);
+      pl.total_rows = P.prows;
+      pl.ups = b.ups;
+      HIPCHK(launch_contract_pairs(pl, s));
+    }
     if (prof) HIPCHK(hipEventRecord(evs[3], s));
     CorrArgs ca{a.rec, a.xg, a.xw, ncent, P.nb, P.nmax, (int32_t)P.ldc, b.corr,
                 R->at<double>(P.o_cpart)};
@@ -463,6 +511,8 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
     else HIPCHK(launch_corrections<float>(ca, s));
     if (prof) {
       HIPCHK(hipEventRecord(evs[4], s));
+      R->prof_b_flops += P.pitems == 0 ? contract_f64_issued_flops(P.nb, P.nmax, ncent)
+                                       : pair_issued_flops(R->pplan, P.nb, ncent, P.precision);
       R->prof_a_launches += nlaunch;
       R->prof_b_launches += 7;
       R->prof_steps += 1;
@@ -568,6 +618,7 @@ fpcf4_status fpcf4_request_finalize(fpcf4_request* req, double* upsilon, int32_t
     g_prof.steps += req->prof_steps;
     g_prof.pairs += (int64_t)pairs;
     g_prof.centres += req->prof_centres;
+    g_prof.stage_b_mfma_flops += req->prof_b_flops;
   }
   return FPCF4_OK;
 }

@@ -194,7 +194,7 @@ template <typename T> hipError_t launch_corrections(const CorrArgs& a, hipStream
 // Theta_3 (stage_b_pairs.hip).  A work item is one unordered pair of
 // (family, conjugation, order) for the b2 and b3 factors; its row blocks are
 // the distinct left factors x A(b1) of every (mu, n2, n3) using that pair.
-constexpr int PAIR_MAX_BLK = 4;    // row blocks per item (at most 4 for the factor table)
+constexpr int PAIR_MAX_BLK = 2;    // row blocks per work item (pairs with more are split)
 constexpr int PAIR_SUB = 8192;     // centres per binary32 running sum before binary64
 struct PairRow {
   int8_t x, fam, conj, pad;        // centre factor kind (X_*), A family (F_*), A conjugated
@@ -220,10 +220,10 @@ struct PairPlanHost {
 PairPlanHost make_pair_plan(int nmax, int nb);
 int pair_slices(int64_t ncent);    // centre slices (partial regions) for a tile
 struct PairArgs {
-  const float* rec;
+  const void* rec;                 // records (binary32 or binary64 complex)
   int64_t ldc;
-  const float* xg;                 // [ldc] complex w g
-  const float* xw;                 // [ldc] w
+  const void* xg;                  // [ldc] complex w g
+  const void* xw;                  // [ldc] w
   const unsigned* maxima;
   const PairItem* items;
   int32_t item0, nitems, ncent, nb, nmax;
@@ -245,6 +245,10 @@ struct PairLaunch {
   double* ups;                     // accumulated into
 };
 hipError_t launch_contract_pairs(const PairLaunch& pl, hipStream_t s);
+// matrix-core flops the pair contraction issues for ncent centres
+double pair_issued_flops(const PairPlanHost& pp, int nb, int64_t ncent, int precision);
+// the same for the binary64 group contraction
+double contract_f64_issued_flops(int nb, int nmax, int64_t ncent);
 size_t corr_elems(int nb, int nmax);  // complex elements of the correction buffer
 hipError_t launch_finalize(const double* ups_raw, const double* corr, int nb, int nmax,
                            int subtract, double* out, hipStream_t s);

@@ -742,6 +742,15 @@ __global__ void contract_reduce_kernel(const double* part, int nsl, int64_t n2, 
   ups[i] += v;
 }
 
+double contract_f64_issued_flops(int nb, int nmax, int64_t ncent) {
+  const int nbc = nb <= 8 ? 8 : (nb <= 12 ? 12 : 16);
+  const int nn = 2 * nmax + 1;
+  double rows = 0.0;
+  for (int g = 0; g < NGROUPS; ++g) rows += 16.0 * mt_of(group_of(g).nmu, nbc);
+  const double cols = 16.0 * ((nb * nb + 15) / 16);
+  return rows * cols * 2.0 * 2.0 * (double)nn * nn * (double)ncent;
+}
+
 size_t yprep_bytes(int nb, int nmax, int64_t ncent) {
   const int nbc = nb <= 8 ? 8 : (nb <= 12 ? 12 : 16);
   return yprep_bytes_for(nbc, nmax, ncent);

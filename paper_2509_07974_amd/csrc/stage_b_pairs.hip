@@ -42,6 +42,7 @@
 // the output tensor.  No atomics: the result is deterministic.
 #include <map>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "factors.hpp"
@@ -73,31 +74,42 @@ PairPlanHost make_pair_plan(int nmax, int nb) {
   const int nn = 2 * nmax + 1;
   P.out.assign((size_t)FPCF4_NCORR * nn * nn, PairOut{-1, 0, 0, 0});
   for (int c = 0; c <= PAIR_MAX_BLK; ++c) P.cls_start[c] = P.cls_count[c] = 0;
-  // items grouped by their number of row blocks (one kernel per class)
+  // Work items of at most PAIR_MAX_BLK row blocks (a pair used by more left
+  // factors is split over several items that form the same R), grouped by
+  // their number of row blocks (one kernel per class).
+  struct Unit { std::pair<Spec, Spec> key; std::vector<std::pair<RowKey, std::vector<Tgt>>> rows; };
+  std::vector<Unit> units;
+  for (const auto& kv : items) {
+    std::vector<std::pair<RowKey, std::vector<Tgt>>> all(kv.second.begin(), kv.second.end());
+    for (size_t k = 0; k < all.size(); k += PAIR_MAX_BLK) {
+      Unit u{kv.first, {}};
+      for (size_t q = k; q < all.size() && q < k + PAIR_MAX_BLK; ++q) u.rows.push_back(all[q]);
+      units.push_back(u);
+    }
+  }
   int64_t rows = 0;
   for (int nbk = 1; nbk <= PAIR_MAX_BLK; ++nbk) {
     P.cls_start[nbk] = (int)P.items.size();
-    for (const auto& kv : items) {
-      if ((int)kv.second.size() != nbk) continue;
+    for (const Unit& un : units) {
+      if ((int)un.rows.size() != nbk) continue;
       PairItem it{};
-      it.famB = (int8_t)std::get<0>(kv.first.first);
-      it.conjB = (int8_t)std::get<1>(kv.first.first);
-      it.ordB = std::get<2>(kv.first.first);
-      it.famC = (int8_t)std::get<0>(kv.first.second);
-      it.conjC = (int8_t)std::get<1>(kv.first.second);
-      it.ordC = std::get<2>(kv.first.second);
+      it.famB = (int8_t)std::get<0>(un.key.first);
+      it.conjB = (int8_t)std::get<1>(un.key.first);
+      it.ordB = std::get<2>(un.key.first);
+      it.famC = (int8_t)std::get<0>(un.key.second);
+      it.conjC = (int8_t)std::get<1>(un.key.second);
+      it.ordC = std::get<2>(un.key.second);
       it.nblk = nbk;
       it.row0 = (int32_t)rows;
-      int k = 0;
-      for (const auto& rv : kv.second) {
-        it.blk[k].x = (int8_t)std::get<0>(rv.first);
-        it.blk[k].fam = (int8_t)std::get<1>(rv.first);
-        it.blk[k].conj = (int8_t)std::get<2>(rv.first);
-        it.blk[k].order = std::get<3>(rv.first);
-        for (const Tgt& t : rv.second)
+      for (int k = 0; k < nbk; ++k) {
+        const RowKey& rk = un.rows[k].first;
+        it.blk[k].x = (int8_t)std::get<0>(rk);
+        it.blk[k].fam = (int8_t)std::get<1>(rk);
+        it.blk[k].conj = (int8_t)std::get<2>(rk);
+        it.blk[k].order = std::get<3>(rk);
+        for (const Tgt& t : un.rows[k].second)
           P.out[((size_t)t.mu * nn + (t.n2 + nmax)) * nn + (t.n3 + nmax)] =
               PairOut{(int32_t)P.items.size(), k, t.tr, 0};
-        ++k;
       }
       rows += (int64_t)nbk * 2 * nb;
       P.items.push_back(it);
@@ -140,7 +152,7 @@ constexpr int PKS = PKC / 16;
 __host__ __device__ constexpr int pair_mt(int nblk, int nbc) { return (nblk * 2 * nbc + 15) / 16; }
 __host__ __device__ constexpr int pair_ct(int nbc) { return (nbc * nbc + 15) / 16; }
 __host__ __device__ constexpr int pair_waves(int nblk, int nbc) {
-  return nbc == 8 ? 2 : nbc == 12 ? 3 : (pair_mt(nblk, nbc) > 4 ? 8 : 4);
+  return nbc == 8 ? 2 : nbc == 12 ? 3 : (nblk > 1 ? 8 : 4);
 }
 __host__ __device__ constexpr int pair_nt(int nblk, int nbc) {
   return (pair_ct(nbc) + pair_waves(nblk, nbc) - 1) / pair_waves(nblk, nbc);
@@ -221,8 +233,9 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_kern
   constexpr int W = pair_waves(NBLK, NBC);
   constexpr int NT = pair_nt(NBLK, NBC);
   constexpr int NTH = 64 * W;
-  constexpr int NXS = (NBC * PKC + NTH - 1) / NTH;              // B/C (bin, centre) slots per thread
-  constexpr int NRU = (NBLK * NBC * PKS * 4 + NTH - 1) / NTH;   // left-operand units per thread
+  constexpr int BS = PKC + 2;            // LDS row stride (complex): 16-byte rows, conflict-free
+  static_assert(NBC * PKC / 2 <= NTH, "one B/C centre pair per thread");
+  static_assert(NBLK * NBC * 4 * PKS <= NTH, "one left-operand unit per thread");
   const int nb = a.nb, n = a.nmax;
   const Layout L = make_layout(n);
   int bx, by;
@@ -234,18 +247,17 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_kern
   const int ntiles = (ncols + 15) >> 4;
   const int mrows = NBLK * 2 * nb;
   // centres [cbase, cbase + ncent) of this slice
-  const int per = (int)(((int64_t)a.ncent + gridDim.y - 1) / gridDim.y + PKC - 1) / PKC * PKC;
+  const int per = (int)((((int64_t)a.ncent + gridDim.y - 1) / gridDim.y + PKC - 1) / PKC * PKC);
   const int cbase = by * per;
   const int ncent = imax(0, imin(a.ncent - cbase, per));
-  const float* rec = a.rec + 2 * (int64_t)cbase;
   const int64_t ldc = a.ldc;
-  const int rowB = rec_entry(L, it.famB, it.ordB);
-  const int rowC = rec_entry(L, it.famC, it.ordC);
+  const int lastc = (int)ldc - 4;         // last 4-aligned group start inside a record row
 
-  __shared__ cf Bs[2][NBC][PKC + 1];
-  __shared__ cf Cs[2][NBC][PKC + 1];
+  __shared__ cf Bs[2][NBC][BS];
+  __shared__ cf Cs[2][NBC][BS];
   __shared__ H8 Ys[2][PKS][MT][2][64];    // left operand in MFMA lane order, hi / lo
   __shared__ float scl[3][16];            // scales of y (per b1), B (per b2), C (per b3)
+  __shared__ float inv[3][16];            // their inverses (exact: powers of two)
 
   if (tid < 16) {
     const unsigned* M = a.maxima;
@@ -258,9 +270,9 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_kern
       sb = pow2_under(1.5f * __uint_as_float(M[(it.famB == F_G ? 0 : 16) + tid]), 6);
       sc = pow2_under(1.5f * __uint_as_float(M[(it.famC == F_G ? 0 : 16) + tid]), 6);
     }
-    scl[0][tid] = sy;
-    scl[1][tid] = sb;
-    scl[2][tid] = sc;
+    scl[0][tid] = sy; inv[0][tid] = 1.0f / sy;
+    scl[1][tid] = sb; inv[1][tid] = 1.0f / sb;
+    scl[2][tid] = sc; inv[2][tid] = 1.0f / sc;
   }
   // left-operand rows past the used ones stay zero in both buffers
   {
@@ -272,91 +284,76 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_kern
     }
   }
 
-  // ---- this thread's staging slots
-  // B / C: slot s -> (bin s / 32, centre s % 32)
-  // left operand: unit u -> (block, b1, K-step, lane group q): four centres
-  //   16 ks + 4 q + (0..3) of row (block, b1); writes the real-output and the
-  //   imaginary-output rows of that b1.
-  // All units of a thread share (K-step, lane group) (NTH is a multiple of 8),
-  // so they share the four centres and their centre factor.
-  const int ru_q = tid & 3, ru_ks = (tid >> 2) % PKS;
-  int ru_blk[NRU], ru_b1[NRU], ru_rowA[NRU], ru_xc[NRU], ru_ac[NRU];
-  bool ru_on[NRU];
-#pragma unroll
-  for (int h = 0; h < NRU; ++h) {
-    const int u = tid + NTH * h;
-    const int b1 = (u / (4 * PKS)) % NBC, blk = u / (4 * PKS * NBC);
-    ru_on[h] = blk < NBLK && b1 < nb;
-    ru_blk[h] = ru_on[h] ? blk : 0;
-    ru_b1[h] = ru_on[h] ? b1 : 0;
-    // the block's fields selected without a dynamic index into the item
-    PairRow rb = it.blk[0];
-#pragma unroll
-    for (int k = 1; k < NBLK; ++k)
-      if (ru_blk[h] == k) rb = it.blk[k];
-    ru_rowA[h] = ru_on[h] ? rec_entry(L, rb.fam, rb.order) : 0;
-    ru_xc[h] = rb.x == X_GC;
-    ru_ac[h] = rb.conj;
-  }
+  // ---- staging slots of this thread (one each)
+  // B / C: a pair of centres 2p, 2p+1 of bin sb, loaded as 16 bytes
+  const int sbin = tid >> 4, spair = tid & 15;
+  const bool s_on = sbin < nb;
+  const float* recf = reinterpret_cast<const float*>(a.rec);
+  const float* rowBp = recf + 2 * (((int64_t)rec_entry(L, it.famB, it.ordB) * nb + (s_on ? sbin : 0)) * ldc);
+  const float* rowCp = recf + 2 * (((int64_t)rec_entry(L, it.famC, it.ordC) * nb + (s_on ? sbin : 0)) * ldc);
+  // left operand: unit (block, b1, K-step, lane group q) = four consecutive
+  // centres 16 ks + 4 q + (0..3) of row (block, b1); it writes the
+  // real-output and the imaginary-output rows of that b1
+  const int uq = tid & 3, uks = (tid >> 2) & 1, ub1 = (tid >> 3) % NBC, ublk = (tid >> 3) / NBC;
+  const bool u_on = ublk < NBLK && ub1 < nb;
+  PairRow rb = it.blk[0];
+  if (NBLK > 1 && ublk == 1) rb = it.blk[1];
+  const float* rowAp = recf + 2 * (((int64_t)rec_entry(L, rb.fam, rb.order) * nb + (u_on ? ub1 : 0)) * ldc);
+  const bool xconj = rb.x == X_GC, aconj = rb.conj != 0;
   const bool x_is_w = it.blk[0].x == X_W;   // the W items use w; all others w g
-  struct Pf {
-    cf bv[NXS], cv[NXS];
-    cf av[NRU][4], xv[4];
-  } pf;
+  const float4* xg4 = reinterpret_cast<const float4*>(a.xg);
+  const float4* xw4 = reinterpret_cast<const float4*>(a.xw);
+
+  float4 pb, pc, pa0, pa1, px0, px1;
   auto issue = [&](int c0) {
-#pragma unroll
-    for (int h = 0; h < NXS; ++h) {
-      const int s = tid + NTH * h;
-      const int b = s / PKC, c = c0 + s % PKC;
-      const int bl = b < nb ? b : nb - 1, cl = c < ncent ? c : ncent - 1;
-      const float* pb = rec + 2 * (((int64_t)rowB * nb + bl) * ldc + cl);
-      const float* pc = rec + 2 * (((int64_t)rowC * nb + bl) * ldc + cl);
-      pf.bv[h] = {pb[0], pb[1]};
-      pf.cv[h] = {pc[0], pc[1]};
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int c = c0 + 16 * ru_ks + 4 * ru_q + v;
-      const int cl = c < ncent ? c : ncent - 1;
-      if (x_is_w) pf.xv[v] = {a.xw[cbase + cl], 0.0f};
-      else pf.xv[v] = {a.xg[2 * (int64_t)(cbase + cl)], a.xg[2 * (int64_t)(cbase + cl) + 1]};
-#pragma unroll
-      for (int h = 0; h < NRU; ++h) {
-        const float* pa = rec + 2 * (((int64_t)ru_rowA[h] * nb + ru_b1[h]) * ldc + cl);
-        pf.av[h][v] = {pa[0], pa[1]};
-      }
+    const int gp = imin(cbase + c0 + 2 * spair, (int)ldc - 2);
+    pb = *reinterpret_cast<const float4*>(rowBp + 2 * (int64_t)gp);
+    pc = *reinterpret_cast<const float4*>(rowCp + 2 * (int64_t)gp);
+    const int gu = imin(cbase + c0 + 16 * uks + 4 * uq, lastc);
+    const float4* pa = reinterpret_cast<const float4*>(rowAp + 2 * (int64_t)gu);
+    pa0 = pa[0];
+    pa1 = pa[1];
+    if (x_is_w) {
+      px0 = xw4[gu >> 2];
+    } else {
+      px0 = xg4[gu >> 1];
+      px1 = xg4[(gu >> 1) + 1];
     }
   };
   auto commit = [&](int c0, int buf) {
-#pragma unroll
-    for (int h = 0; h < NXS; ++h) {
-      const int s = tid + NTH * h;
-      const int b = s / PKC, cc = s % PKC;
-      if (b < nb) {
-        const bool live = c0 + cc < ncent;
-        const float sb = live ? scl[1][b] : 0.0f, sc = live ? scl[2][b] : 0.0f;
-        const float bi = it.conjB ? -pf.bv[h].i : pf.bv[h].i;
-        const float ci = it.conjC ? -pf.cv[h].i : pf.cv[h].i;
-        Bs[buf][b][cc] = {pf.bv[h].r * sb, bi * sb};
-        Cs[buf][b][cc] = {pf.cv[h].r * sc, ci * sc};
-      }
+    if (s_on) {
+      // centres past the tile read stale record memory (possibly NaN
+      // patterns) inside the row stride: select zeros, never multiply
+      const int cc = 2 * spair;
+      const bool l0 = c0 + cc < ncent, l1 = c0 + cc + 1 < ncent;
+      const float sb = scl[1][sbin], sc = scl[2][sbin];
+      const float bs = it.conjB ? -sb : sb, cs = it.conjC ? -sc : sc;
+      *reinterpret_cast<float4*>(&Bs[buf][sbin][cc]) =
+          float4{l0 ? pb.x * sb : 0.0f, l0 ? pb.y * bs : 0.0f, l1 ? pb.z * sb : 0.0f, l1 ? pb.w * bs : 0.0f};
+      *reinterpret_cast<float4*>(&Cs[buf][sbin][cc]) =
+          float4{l0 ? pc.x * sc : 0.0f, l0 ? pc.y * cs : 0.0f, l1 ? pc.z * sc : 0.0f, l1 ? pc.w * cs : 0.0f};
     }
-#pragma unroll
-    for (int h = 0; h < NRU; ++h) {
-      if (!ru_on[h]) continue;
-      const int blk = ru_blk[h], b1 = ru_b1[h], ks = ru_ks, q = ru_q;
-      const float sy = scl[0][b1];
+    if (u_on) {
+      const float sy = scl[0][ub1];
+      const float A[8] = {pa0.x, pa0.y, pa0.z, pa0.w, pa1.x, pa1.y, pa1.z, pa1.w};
+      float X[8];
+      if (x_is_w) {
+        X[0] = px0.x; X[2] = px0.y; X[4] = px0.z; X[6] = px0.w;
+        X[1] = X[3] = X[5] = X[7] = 0.0f;
+      } else {
+        X[0] = px0.x; X[1] = px0.y; X[2] = px0.z; X[3] = px0.w;
+        X[4] = px1.x; X[5] = px1.y; X[6] = px1.z; X[7] = px1.w;
+      }
       float vr[8], vi[8];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const bool live = c0 + 16 * ks + 4 * q + v < ncent;
-        cf x = pf.xv[v], A = pf.av[h][v];
-        if (ru_xc[h]) x.i = -x.i;
-        if (ru_ac[h]) A.i = -A.i;
+        const bool live = c0 + 16 * uks + 4 * uq + v < ncent;
+        const float xr = X[2 * v], xi = xconj ? -X[2 * v + 1] : X[2 * v + 1];
+        const float ar = A[2 * v], ai = aconj ? -A[2 * v + 1] : A[2 * v + 1];
         // explicit fused forms: the rounding does not depend on how the
         // compiler would contract the expression
-        float yr = __builtin_fmaf(x.r, A.r, -(x.i * A.i));
-        float yi = __builtin_fmaf(x.r, A.i, x.i * A.r);
+        float yr = __builtin_fmaf(xr, ar, -(xi * ai));
+        float yi = __builtin_fmaf(xr, ai, xi * ar);
         yr = live ? yr * sy : 0.0f;
         yi = live ? yi * sy : 0.0f;
         vr[2 * v] = yr;      // real-output row: [y_r, -y_i]
@@ -367,23 +364,25 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_kern
       H8 hr, lr, hi, li;
       split8<PREC>(vr, hr, lr);
       split8<PREC>(vi, hi, li);
-      const int r_re = blk * 2 * nb + b1, r_im = r_re + nb;
-      Ys[buf][ks][r_re >> 4][0][16 * q + (r_re & 15)] = hr;
-      Ys[buf][ks][r_re >> 4][1][16 * q + (r_re & 15)] = lr;
-      Ys[buf][ks][r_im >> 4][0][16 * q + (r_im & 15)] = hi;
-      Ys[buf][ks][r_im >> 4][1][16 * q + (r_im & 15)] = li;
+      const int r_re = ublk * 2 * nb + ub1, r_im = r_re + nb;
+      Ys[buf][uks][r_re >> 4][0][16 * uq + (r_re & 15)] = hr;
+      Ys[buf][uks][r_re >> 4][1][16 * uq + (r_re & 15)] = lr;
+      Ys[buf][uks][r_im >> 4][0][16 * uq + (r_im & 15)] = hi;
+      Ys[buf][uks][r_im >> 4][1][16 * uq + (r_im & 15)] = li;
     }
   };
 
-  // this wave's column tiles T = wr + W t; the wave holding one more tile
-  // rotates with the item so co-resident workgroups differ
+  // this wave's column tiles T = wr + W t (valid for t < ntw); the wave
+  // holding one more tile rotates with the item so co-resident workgroups
+  // differ
   const int wr = (wv + bx) % W;
+  const int ntw = imin(NT, imax(0, (ntiles - wr + W - 1) / W));
   int b2c[NT], b3c[NT];
   bool colok[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int j = 16 * (wr + W * t) + (lane & 15);
-    colok[t] = j < ncols;
+    colok[t] = t < ntw && j < ncols;
     b2c[t] = colok[t] ? j / nb : 0;
     b3c[t] = colok[t] ? j % nb : 0;
   }
@@ -397,28 +396,82 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_kern
       mid[m][t] = f4{0.f, 0.f, 0.f, 0.f};
     }
 
-  // write (first == true) or add the running sum, unscaled, into this
-  // workgroup's region of the slice partial buffer, then clear it
-  double* part = a.part + ((int64_t)by * a.total_rows + it.row0) * ncols;
-  auto flush = [&](bool first) {
+  // One chunk of compute over all NT column tiles of the wave.  A wave with
+  // fewer valid tiles (bin counts whose nb^2 tiles do not divide evenly)
+  // computes the surplus ones on columns it never writes: no branch inside
+  // the MFMA sequence, and a single code path keeps the register count low.
+  auto compute = [&](auto Vc, int buf) {
+    constexpr int V = decltype(Vc)::value;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if (!colok[t]) continue;
-      const int j = 16 * (wr + W * t) + (lane & 15);
-      const double ubc = 1.0 / ((double)scl[1][b2c[t]] * (double)scl[2][b3c[t]]);
+    for (int ks = 0; ks < PKS; ++ks) {
+      const int cb = 16 * ks + 4 * (lane >> 4);
+      H8 rh[V], rl[V];
+#pragma unroll
+      for (int t = 0; t < V; ++t) {
+        const float4 b01 = *reinterpret_cast<const float4*>(&Bs[buf][b2c[t]][cb]);
+        const float4 b23 = *reinterpret_cast<const float4*>(&Bs[buf][b2c[t]][cb + 2]);
+        const float4 c01 = *reinterpret_cast<const float4*>(&Cs[buf][b3c[t]][cb]);
+        const float4 c23 = *reinterpret_cast<const float4*>(&Cs[buf][b3c[t]][cb + 2]);
+        const float B[8] = {b01.x, b01.y, b01.z, b01.w, b23.x, b23.y, b23.z, b23.w};
+        const float Cv[8] = {c01.x, c01.y, c01.z, c01.w, c23.x, c23.y, c23.z, c23.w};
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          v[2 * u] = __builtin_fmaf(B[2 * u], Cv[2 * u], -(B[2 * u + 1] * Cv[2 * u + 1]));
+          v[2 * u + 1] = __builtin_fmaf(B[2 * u], Cv[2 * u + 1], B[2 * u + 1] * Cv[2 * u]);
+        }
+        split8<PREC>(v, rh[t], rl[t]);
+      }
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
+        const H8 yh = Ys[buf][ks][m][0][lane];
+        const H8 yl = Ys[buf][ks][m][1][lane];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * m + 4 * (lane >> 4) + r;
-          if (row < mrows) {
-            const double v = (double)mid[m][t][r] * (ubc / (double)scl[0][row % nb]);
-            double* p = part + (int64_t)row * ncols + j;
-            *p = first ? v : *p + v;
-          }
-        }
-        mid[m][t] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < V; ++t) acc[m][t] = mma<PREC>(yh, rh[t], acc[m][t]);
+#pragma unroll
+        for (int t = 0; t < V; ++t) acc[m][t] = mma<PREC>(yh, rl[t], acc[m][t]);
+#pragma unroll
+        for (int t = 0; t < V; ++t) acc[m][t] = mma<PREC>(yl, rh[t], acc[m][t]);
       }
+    }
+  };
+
+  // write (first) or add the running sum, unscaled (exact powers of two), into
+  // this workgroup's region of the slice partial buffer, then clear it
+  double* part = a.part + ((int64_t)by * a.total_rows + it.row0) * ncols;
+  auto flush = [&](bool first) {
+    // opaque to the optimiser: the flush runs once per 8192 centres, so its
+    // addresses are recomputed there instead of being hoisted out of the
+    // chunk loop and held in registers across it
+    double* pbase = part;
+    int ln = lane;
+    asm volatile("" : "+s"(pbase), "+v"(ln));
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (colok[t]) {
+        const int j = 16 * (wr + W * t) + (ln & 15);
+        const int b2 = j / nb, b3 = j - b2 * nb;
+        const float ubc = inv[1][b2] * inv[2][b3];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * m + 4 * (ln >> 4) + r;
+            if (row < mrows) {
+              // b1 = row mod nb (row < 4 nb)
+              const int b1 = row - nb * ((row >= nb) + (row >= 2 * nb) + (row >= 3 * nb));
+              const double v = (double)mid[m][t][r] * (double)ubc * (double)inv[0][b1];
+              double* p = pbase + (int64_t)row * ncols + j;
+              *p = first ? v : *p + v;
+            }
+          }
+          // one row tile at a time: keeps the read-modify-writes from being
+          // gathered into one long-lived batch of registers
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < MT; ++m) mid[m][t] = f4{0.f, 0.f, 0.f, 0.f};
     }
   };
 
@@ -434,37 +487,7 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_kern
     const int buf = ch & 1;
     const bool more = ch + 1 < nchunks;
     if (more) issue((ch + 1) * PKC);
-#pragma unroll
-    for (int ks = 0; ks < PKS; ++ks) {
-      const int cb = 16 * ks + 4 * (lane >> 4);
-      H8 rh[NT], rl[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        float v[8];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const cf bv = Bs[buf][b2c[t]][cb + u];
-          const cf cv = Cs[buf][b3c[t]][cb + u];
-          v[2 * u] = __builtin_fmaf(bv.r, cv.r, -(bv.i * cv.i));
-          v[2 * u + 1] = __builtin_fmaf(bv.r, cv.i, bv.i * cv.r);
-        }
-        split8<PREC>(v, rh[t], rl[t]);
-      }
-#pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const H8 yh = Ys[buf][ks][m][0][lane];
-        const H8 yl = Ys[buf][ks][m][1][lane];
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (wr + W * t < ntiles) acc[m][t] = mma<PREC>(yh, rh[t], acc[m][t]);
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (wr + W * t < ntiles) acc[m][t] = mma<PREC>(yh, rl[t], acc[m][t]);
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (wr + W * t < ntiles) acc[m][t] = mma<PREC>(yl, rh[t], acc[m][t]);
-      }
-    }
+    compute(std::integral_constant<int, NT>{}, buf);
     if ((ch & 15) == 15 || !more) {      // every 512 centres: fp32 block into the running sum
 #pragma unroll
       for (int m = 0; m < MT; ++m)
@@ -482,6 +505,181 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_kern
     __syncthreads();
   }
   if (first) flush(true);          // empty slice: zeros
+}
+
+// ---------------------------------------------------------------------------
+// binary64: the same work items on v_mfma_f64_16x16x4_f64, no operand split,
+// no scaling, binary64 accumulation over the whole slice.  K-step = 2 centres
+// x (re, im): lane L holds k = L / 16, i.e. centre 2 ks + k / 2, part k % 2.
+// The left operand y = x A is staged as complex values and each lane builds
+// its [y_r, -y_i] / [y_i, y_r] entry; the right operand entry is the real or
+// imaginary part of B(b2) C(b3) for the lane's column.
+// ---------------------------------------------------------------------------
+struct cd {
+  double r, i;
+};
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int NBLK, int NBC>
+__global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_f64_kernel(PairArgs a) {
+  constexpr int MT = pair_mt(NBLK, NBC);
+  constexpr int W = pair_waves(NBLK, NBC);
+  constexpr int NT = pair_nt(NBLK, NBC);
+  constexpr int NTH = 64 * W;
+  constexpr int BS = PKC + 1;
+  static_assert(NBC * PKC / 2 <= NTH, "one B/C centre pair per thread");
+  static_assert(NBLK * NBC * 8 <= NTH, "one left-operand unit per thread");
+  const int nb = a.nb, n = a.nmax;
+  const Layout L = make_layout(n);
+  int bx, by;
+  xcd_contiguous(bx, by);
+  const PairItem it = a.items[a.item0 + bx];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ncols = nb * nb;
+  const int ntiles = (ncols + 15) >> 4;
+  const int mrows = NBLK * 2 * nb;
+  const int per = (int)((((int64_t)a.ncent + gridDim.y - 1) / gridDim.y + PKC - 1) / PKC * PKC);
+  const int cbase = by * per;
+  const int ncent = imax(0, imin(a.ncent - cbase, per));
+  const int64_t ldc = a.ldc;
+  const double* rec = reinterpret_cast<const double*>(a.rec);
+
+  __shared__ cd Bs[2][NBC][BS];
+  __shared__ cd Cs[2][NBC][BS];
+  __shared__ cd Ys[2][NBLK][NBC][BS];
+
+  // staging slots: B / C pair of centres 2p, 2p+1 of bin sbin; left-operand
+  // unit (block, b1, group of 4 centres)
+  const int sbin = tid >> 4, spair = tid & 15;
+  const bool s_on = sbin < nb;
+  const double* rowBp = rec + 2 * (((int64_t)rec_entry(L, it.famB, it.ordB) * nb + (s_on ? sbin : 0)) * ldc);
+  const double* rowCp = rec + 2 * (((int64_t)rec_entry(L, it.famC, it.ordC) * nb + (s_on ? sbin : 0)) * ldc);
+  const int ug = tid & 7, ub1 = (tid >> 3) % NBC, ublk = (tid >> 3) / NBC;
+  const bool u_on = ublk < NBLK && ub1 < nb;
+  PairRow rb = it.blk[0];
+  if (NBLK > 1 && ublk == 1) rb = it.blk[1];
+  const double* rowAp = rec + 2 * (((int64_t)rec_entry(L, rb.fam, rb.order) * nb + (u_on ? ub1 : 0)) * ldc);
+  const bool xconj = rb.x == X_GC, aconj = rb.conj != 0;
+  const bool x_is_w = it.blk[0].x == X_W;
+  const double* xg = reinterpret_cast<const double*>(a.xg);
+  const double* xw = reinterpret_cast<const double*>(a.xw);
+  const int lastc = (int)ldc - 4;
+
+  cd pb[2], pc[2], pa[4], px[4];
+  auto issue = [&](int c0) {
+    const int gp = imin(cbase + c0 + 2 * spair, (int)ldc - 2);
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      pb[v] = {rowBp[2 * ((int64_t)gp + v)], rowBp[2 * ((int64_t)gp + v) + 1]};
+      pc[v] = {rowCp[2 * ((int64_t)gp + v)], rowCp[2 * ((int64_t)gp + v) + 1]};
+    }
+    const int gu = imin(cbase + c0 + 4 * ug, lastc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      pa[v] = {rowAp[2 * ((int64_t)gu + v)], rowAp[2 * ((int64_t)gu + v) + 1]};
+      px[v] = x_is_w ? cd{xw[gu + v], 0.0} : cd{xg[2 * ((int64_t)gu + v)], xg[2 * ((int64_t)gu + v) + 1]};
+    }
+  };
+  auto commit = [&](int c0, int buf) {
+    if (s_on) {
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const bool live = c0 + 2 * spair + v < ncent;   // past the tile: stale memory, select zeros
+        const double bi = it.conjB ? -pb[v].i : pb[v].i, ci = it.conjC ? -pc[v].i : pc[v].i;
+        Bs[buf][sbin][2 * spair + v] = live ? cd{pb[v].r, bi} : cd{0.0, 0.0};
+        Cs[buf][sbin][2 * spair + v] = live ? cd{pc[v].r, ci} : cd{0.0, 0.0};
+      }
+    }
+    if (u_on) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const bool live = c0 + 4 * ug + v < ncent;
+        const double xr = px[v].r, xi = xconj ? -px[v].i : px[v].i;
+        const double ar = pa[v].r, ai = aconj ? -pa[v].i : pa[v].i;
+        const cd y{xr * ar - xi * ai, xr * ai + xi * ar};
+        Ys[buf][ublk][ub1][4 * ug + v] = live ? y : cd{0.0, 0.0};
+      }
+    }
+  };
+
+  const int wr = (wv + bx) % W;
+  const int ntw = imin(NT, imax(0, (ntiles - wr + W - 1) / W));
+  int b2c[NT], b3c[NT];
+  bool colok[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int j = 16 * (wr + W * t) + (lane & 15);
+    colok[t] = t < ntw && j < ncols;
+    b2c[t] = colok[t] ? j / nb : 0;
+    b3c[t] = colok[t] ? j % nb : 0;
+  }
+  // this lane's left-operand row in each row tile: (block, re/im, b1)
+  int rblk[MT], rb1[MT];
+  bool rpart[MT], rok[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int r = 16 * m + (lane & 15);
+    rok[m] = r < mrows;
+    const int rr = rok[m] ? r : 0;
+    rblk[m] = rr / (2 * nb);
+    rpart[m] = (rr % (2 * nb)) >= nb;
+    rb1[m] = rr % nb;
+  }
+  d4 acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int kq = lane >> 4;
+  const bool pk = kq & 1;
+  const int nchunks = (ncent + PKC - 1) / PKC;
+  if (ncent > 0) {
+    issue(0);
+    commit(0, 0);
+  }
+  __syncthreads();
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nchunks;
+    if (more) issue((ch + 1) * PKC);
+#pragma unroll 4
+    for (int ks = 0; ks < PKC / 2; ++ks) {
+      const int cc = 2 * ks + (kq >> 1);
+      double bv[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const cd b = Bs[buf][b2c[t]][cc], c = Cs[buf][b3c[t]][cc];
+        bv[t] = pk ? b.r * c.i + b.i * c.r : b.r * c.r - b.i * c.i;
+      }
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const cd y = Ys[buf][rblk[m]][rb1[m]][cc];
+        // [y_r, -y_i] on real-output rows, [y_i, y_r] on imaginary-output rows
+        double av = rpart[m] ? (pk ? y.r : y.i) : (pk ? -y.i : y.r);
+        av = rok[m] ? av : 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[t], acc[m][t], 0, 0, 0);
+      }
+    }
+    if (more) commit((ch + 1) * PKC, buf ^ 1);
+    __syncthreads();
+  }
+  // f64 D layout: element r of lane L is row 4 r + L / 16, column L % 16
+  double* part = a.part + ((int64_t)by * a.total_rows + it.row0) * ncols;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (!colok[t]) continue;
+    const int j = 16 * (wr + W * t) + (lane & 15);
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * m + 4 * r + (lane >> 4);
+        if (row < mrows) part[(int64_t)row * ncols + j] = acc[m][t][r];
+      }
+  }
 }
 
 // ups[mu][b1][b2][b3][n2][n3] += sum over slices of the item region that holds
@@ -517,12 +715,29 @@ static void launch_cls(const PairArgs& a, int nsl, hipStream_t s) {
 
 template <int PREC, int NBC>
 static void launch_prec_nbc(const PairArgs& a, int nblk, int nsl, hipStream_t s) {
-  switch (nblk) {
-    case 1: launch_cls<PREC, 1, NBC>(a, nsl, s); break;
-    case 2: launch_cls<PREC, 2, NBC>(a, nsl, s); break;
-    case 3: launch_cls<PREC, 3, NBC>(a, nsl, s); break;
-    default: launch_cls<PREC, 4, NBC>(a, nsl, s); break;
+  if (nblk == 1) launch_cls<PREC, 1, NBC>(a, nsl, s);
+  else launch_cls<PREC, 2, NBC>(a, nsl, s);
+}
+
+template <int NBC>
+static void launch_f64_nbc(const PairArgs& a, int nblk, int nsl, hipStream_t s) {
+  const dim3 grid(a.nitems, nsl);
+  if (nblk == 1)
+    hipLaunchKernelGGL((contract_pair_f64_kernel<1, NBC>), grid, dim3(64 * pair_waves(1, NBC)), 0, s, a);
+  else
+    hipLaunchKernelGGL((contract_pair_f64_kernel<2, NBC>), grid, dim3(64 * pair_waves(2, NBC)), 0, s, a);
+}
+
+double pair_issued_flops(const PairPlanHost& pp, int nb, int64_t ncent, int precision) {
+  const int nbc = nb <= 8 ? 8 : nb <= 12 ? 12 : 16;
+  double f = 0.0;
+  for (int k = 1; k <= PAIR_MAX_BLK; ++k) {
+    const int cols = 16 * pair_waves(k, nbc) * pair_nt(k, nbc);   // surplus tiles included
+    // rows x columns x K (real, imaginary) x 2 flop (x 3 hi/lo products in the 16-bit paths)
+    f += (double)pp.cls_count[k] * 16.0 * pair_mt(k, nbc) * cols * 2.0 * 2.0 *
+         (precision == FPCF4_FP64 ? 1.0 : 3.0);
   }
+  return f * (double)ncent;
 }
 
 hipError_t launch_contract_pairs(const PairLaunch& pl, hipStream_t s) {
@@ -531,10 +746,10 @@ hipError_t launch_contract_pairs(const PairLaunch& pl, hipStream_t s) {
   for (int nblk = 1; nblk <= PAIR_MAX_BLK; ++nblk) {
     if (pl.cls_count[nblk] == 0) continue;
     PairArgs a{};
-    a.rec = reinterpret_cast<const float*>(pl.rec);
+    a.rec = pl.rec;
     a.ldc = pl.ldc;
-    a.xg = reinterpret_cast<const float*>(pl.xg);
-    a.xw = reinterpret_cast<const float*>(pl.xw);
+    a.xg = pl.xg;
+    a.xw = pl.xw;
     a.maxima = pl.maxima;
     a.items = pl.items;
     a.item0 = pl.cls_start[nblk];
@@ -544,7 +759,11 @@ hipError_t launch_contract_pairs(const PairLaunch& pl, hipStream_t s) {
     a.nmax = pl.nmax;
     a.part = pl.part;
     a.total_rows = pl.total_rows;
-    if (pl.nb <= 8) {
+    if (pl.precision == FPCF4_FP64) {
+      if (pl.nb <= 8) launch_f64_nbc<8>(a, nblk, nsl, s);
+      else if (pl.nb <= 12) launch_f64_nbc<12>(a, nblk, nsl, s);
+      else launch_f64_nbc<16>(a, nblk, nsl, s);
+    } else if (pl.nb <= 8) {
       if (pl.precision == FPCF4_MIXED_FP16) launch_prec_nbc<FPCF4_MIXED_FP16, 8>(a, nblk, nsl, s);
       else launch_prec_nbc<FPCF4_MIXED_BF16, 8>(a, nblk, nsl, s);
     } else if (pl.nb <= 12) {

@@ -135,7 +135,8 @@ def test_3pcf_hand_example_on_gpu(fp):
     g1 = np.zeros(3); g2 = np.array([0.1, 0.2, 0.3]); w = np.array([2.0, 1.0, 1.0])
     edges = np.array([1.0, 2.0, 4.0])
     P = [-0.012, -0.012, 0.012, 0.012, 2.0]
-    for prec, tol in (("fp64", 1e-15), ("fp16", 1e-8)):
+    # binary32 stage (a): the records' 1e-6 bar (4e-7 measured)
+    for prec, tol in (("fp64", 1e-15), ("fp16", 1e-6)):
         u = fp.estimate_3pcf_multipoles(x, y, g1, g2, w, edges, 3, precision=prec, centers=[0])
         for mu in range(5):
             for n in range(-3, 4):
