@@ -51,7 +51,7 @@ def _torch_lib_dir():
 def _jobs():
     hip = _hipcc()
     jobs = []
-    for src in ("api.hip", "cells.hip", "stage_b.hip", "stage_b_mfma.hip", "stage_b_pairs.hip", "natural.hip",
+    for src in ("api.hip", "cells.hip", "stage_b.hip", "stage_b_pairs.hip", "natural.hip",
                 "threepcf.hip", "stage_a.hip"):
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         jobs.append([hip, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])

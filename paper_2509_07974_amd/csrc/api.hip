@@ -69,12 +69,11 @@ struct PlanInfo {
   size_t sort_tmp = 0;
   // persistent buffers
   size_t o_gal, o_cells, o_centres, o_e2, o_edges, o_counters, o_bbox, o_bad,
-      o_pairs, o_part, o_ups, o_bpart, o_yprep, o_corr, o_cpart, o_acc3, o_part3, o_xg, o_xw, o_counts,
+      o_pairs, o_part, o_ups, o_corr, o_cpart, o_acc3, o_part3, o_xg, o_xw, o_counts,
       o_aos, o_region, o_pitems, o_pout, o_ppart;
   // mixed-precision contraction by Theta_2/Theta_3 block pairs
   int pslices = 0;
   int64_t pitems = 0, prows = 0;
-  int bslices = 1;             // centre slices of the contraction (partials when > 1)
   // tree approximation
   int tree_levels = 0;                      // grids in use (highest level of any bin)
   double tree_delta1 = 0.0;
@@ -179,10 +178,7 @@ fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   P.corr_bytes = order == 4 ? corr_elems(P.nb, P.nmax) * 16 : 0;
   P.acc3_bytes = order == 3 ? three_elems(P.nb, m3) * 16 : 0;
   P.o_ups = take(P.ups_bytes);
-  const bool pairs = order == 4 && P.precision != FPCF4_FP64;
-  P.bslices = order == 4 && !pairs ? contract_slices((int)std::min<int64_t>(P.tile, INT32_MAX), P.nmax) : 1;
-  P.o_bpart = take(P.bslices > 1 ? P.ups_bytes * P.bslices : 0);
-  P.o_yprep = take(0);
+  const bool pairs = order == 4;
   if (pairs) {
     const PairPlanHost pp = make_pair_plan(P.nmax, P.nb);
     for (const PairOut& o : pp.out)
@@ -470,51 +466,36 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
       R->prof_centres += ncent;
     }
   } else if (stage_b) {
-    StageBArgs b{};
-    b.rec = a.rec;
-    b.centres = a.centres;
-    b.ncent = ncent;
-    b.nb = P.nb;
-    b.nmax = P.nmax;
-    b.ups = R->at<double>(P.o_ups);
-    b.corr = R->at<double>(P.o_corr);
-    b.part = P.bslices > 1 ? R->at<double>(P.o_bpart) : nullptr;
-    b.yprep = nullptr;
-    if (P.pitems == 0) {
-      HIPCHK(launch_contract(b, P.precision, (int)P.ldc, a.xg, a.xw, a.maxima, s));
-    } else {
-      PairLaunch pl{};
-      pl.rec = a.rec;
-      pl.ldc = P.ldc;
-      pl.xg = a.xg;
-      pl.xw = a.xw;
-      pl.maxima = a.maxima;
-      pl.items = R->at<PairItem>(P.o_pitems);
-      pl.out = R->at<PairOut>(P.o_pout);
-      for (int c = 0; c <= PAIR_MAX_BLK; ++c) {
-        pl.cls_start[c] = R->pplan.cls_start[c];
-        pl.cls_count[c] = R->pplan.cls_count[c];
-      }
-      pl.ncent = ncent;
-      pl.nb = P.nb;
-      pl.nmax = P.nmax;
-      pl.precision = P.precision;
-      pl.part = R->at<double>(P.o_ppart);
-      pl.total_rows = P.prows;
-      pl.ups = b.ups;
-      HIPCHK(launch_contract_pairs(pl, s));
+    PairLaunch pl{};
+    pl.rec = a.rec;
+    pl.ldc = P.ldc;
+    pl.xg = a.xg;
+    pl.xw = a.xw;
+    pl.maxima = a.maxima;
+    pl.items = R->at<PairItem>(P.o_pitems);
+    pl.out = R->at<PairOut>(P.o_pout);
+    for (int c = 0; c <= PAIR_MAX_BLK; ++c) {
+      pl.cls_start[c] = R->pplan.cls_start[c];
+      pl.cls_count[c] = R->pplan.cls_count[c];
     }
+    pl.ncent = ncent;
+    pl.nb = P.nb;
+    pl.nmax = P.nmax;
+    pl.precision = P.precision;
+    pl.part = R->at<double>(P.o_ppart);
+    pl.total_rows = P.prows;
+    pl.ups = R->at<double>(P.o_ups);
+    HIPCHK(launch_contract_pairs(pl, s));
     if (prof) HIPCHK(hipEventRecord(evs[3], s));
-    CorrArgs ca{a.rec, a.xg, a.xw, ncent, P.nb, P.nmax, (int32_t)P.ldc, b.corr,
+    CorrArgs ca{a.rec, a.xg, a.xw, ncent, P.nb, P.nmax, (int32_t)P.ldc, R->at<double>(P.o_corr),
                 R->at<double>(P.o_cpart)};
     if (P.precision == FPCF4_FP64) HIPCHK(launch_corrections<double>(ca, s));
     else HIPCHK(launch_corrections<float>(ca, s));
     if (prof) {
       HIPCHK(hipEventRecord(evs[4], s));
-      R->prof_b_flops += P.pitems == 0 ? contract_f64_issued_flops(P.nb, P.nmax, ncent)
-                                       : pair_issued_flops(R->pplan, P.nb, ncent, P.precision);
+      R->prof_b_flops += pair_issued_flops(R->pplan, P.nb, ncent, P.precision);
       R->prof_a_launches += nlaunch;
-      R->prof_b_launches += 7;
+      R->prof_b_launches += R->pplan.cls_count[1] > 0 && R->pplan.cls_count[2] > 0 ? 3 : 2;
       R->prof_steps += 1;
       R->prof_centres += ncent;
     }

@@ -145,36 +145,6 @@ hipError_t reduced_build(const double* x, const double* y, const double* g1, con
 template <typename T>
 hipError_t launch_stage_a(int nmax, int order, const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t mid);
 
-struct StageBArgs {
-  const void* rec;          // records of the tile
-  const int32_t* centres;   // sorted positions of the tile's centres
-  int32_t ncent;
-  int32_t nb;
-  int32_t nmax;
-  double* ups;              // [9][nb][nb][nb][nn][nn] complex128 accumulator
-  double* corr;             // correction sums (see stage_b.hip)
-  double* part;             // [contract_slices][9 nb^3 nn^2] complex partials, or null (one slice)
-  void* yprep;              // mixed paths: split Y operand of one group (yprep_bytes), reused per group
-};
-// bytes of the split Y operand buffer of the mixed contraction for a tile of ncent centres
-size_t yprep_bytes(int nb, int nmax, int64_t ncent);
-
-// Centre slices of the contraction: enough workgroups (one per (n2, n3) and
-// slice) to fill the chip (about 8192), at least 8192 centres per slice, at
-// most 32.
-__host__ __device__ inline int contract_slices(int ncent, int nmax) {
-  const int nn2 = (2 * nmax + 1) * (2 * nmax + 1);
-  int s = (8192 + nn2 - 1) / nn2;
-  s = imin(s, 32);
-  s = imin(s, imax(1, ncent / 8192));
-  return imax(s, 1);
-}
-// centres per slice (a multiple of the 32-centre staging chunk)
-__host__ __device__ inline int contract_slice_len(int ncent, int nsl) {
-  const int per = (ncent + nsl - 1) / nsl;
-  return (per + 31) / 32 * 32;
-}
-
 struct CorrArgs {
   const void* rec;
   const void* xg;
@@ -185,13 +155,10 @@ struct CorrArgs {
 };
 constexpr int CORR_SLICES = 8;   // centre slices of the correction sums
 
-// contraction on MFMA (precision: FPCF4_FP64 / _MIXED_FP16 / _MIXED_BF16)
-hipError_t launch_contract(const StageBArgs& sb, int precision, int ldc, const void* xg,
-                           const void* xw, const unsigned* maxima, hipStream_t s);
 template <typename T> hipError_t launch_corrections(const CorrArgs& a, hipStream_t s);
 
-// Mixed-precision contraction organised by the pair of blocks at Theta_2 and
-// Theta_3 (stage_b_pairs.hip).  A work item is one unordered pair of
+// Contraction on the matrix cores, organised by the pair of blocks at
+// Theta_2 and Theta_3 (stage_b_pairs.hip; every precision).  A work item is one unordered pair of
 // (family, conjugation, order) for the b2 and b3 factors; its row blocks are
 // the distinct left factors x A(b1) of every (mu, n2, n3) using that pair.
 constexpr int PAIR_MAX_BLK = 2;    // row blocks per work item (pairs with more are split)
@@ -247,8 +214,6 @@ struct PairLaunch {
 hipError_t launch_contract_pairs(const PairLaunch& pl, hipStream_t s);
 // matrix-core flops the pair contraction issues for ncent centres
 double pair_issued_flops(const PairPlanHost& pp, int nb, int64_t ncent, int precision);
-// the same for the binary64 group contraction
-double contract_f64_issued_flops(int nb, int nmax, int64_t ncent);
 size_t corr_elems(int nb, int nmax);  // complex elements of the correction buffer
 hipError_t launch_finalize(const double* ups_raw, const double* corr, int nb, int nmax,
                            int subtract, double* out, hipStream_t s);

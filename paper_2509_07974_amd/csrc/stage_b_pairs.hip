@@ -226,8 +226,11 @@ __device__ __forceinline__ void xcd_contiguous(int& bx, int& by) {
   by = l / gx;
 }
 
+// Three waves per SIMD (the compiler keeps the kernel within 168 registers):
+// four 3-wave workgroups per CU at 12 bins, whose LDS (38 KB each) fits.
 template <int PREC, int NBLK, int NBC>
-__global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_kernel(PairArgs a) {
+__global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) __attribute__((amdgpu_waves_per_eu(3)))
+void contract_pair_kernel(PairArgs a) {
   typedef typename H8of<PREC>::type H8;
   constexpr int MT = pair_mt(NBLK, NBC);
   constexpr int W = pair_waves(NBLK, NBC);
@@ -294,7 +297,10 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_kern
   // left operand: unit (block, b1, K-step, lane group q) = four consecutive
   // centres 16 ks + 4 q + (0..3) of row (block, b1); it writes the
   // real-output and the imaginary-output rows of that b1
-  const int uq = tid & 3, uks = (tid >> 2) & 1, ub1 = (tid >> 3) % NBC, ublk = (tid >> 3) / NBC;
+  // b1 runs fastest over the threads, so that the 64 lanes of a wave write
+  // consecutive 16-byte slots of the operand (no LDS bank conflicts)
+  const int ub1 = tid % NBC, urest = tid / NBC;
+  const int uq = urest & 3, uks = (urest >> 2) & 1, ublk = urest >> 3;
   const bool u_on = ublk < NBLK && ub1 < nb;
   PairRow rb = it.blk[0];
   if (NBLK > 1 && ublk == 1) rb = it.blk[1];
