@@ -259,6 +259,66 @@ def contract(mp, g1, g2, w, centers, nmax, nb, distinct=True):
     return out
 
 
+def contract_triplets(mp, g1, g2, w, centers, nmax, triplets, distinct=True):
+    """The sums of ``contract`` at the listed radial-bin triplets (b1, b2, b3)
+    only: complex [9, ntrip, 2nmax+1, 2nmax+1].  Each element is the sum over
+    centres of x A(b1) B(b2) C(b3); for distinct quadruplets the App. A.1
+    terms are removed where bins coincide: x c12(b1) C(b3) when b1 = b2,
+    x c13(b1) B(b2) when b1 = b3, x A(b1) c23(b2) when b2 = b3, and twice
+    x t(b1) added back when all three are equal."""
+    t = np.asarray(triplets, dtype=np.int64).reshape(-1, 3)
+    nn = 2 * nmax + 1
+    out = np.zeros((NCORR, len(t), nn, nn), dtype=np.complex128)
+    if len(centers) == 0 or len(t) == 0:
+        return out
+    b1, b2, b3 = t[:, 0], t[:, 1], t[:, 2]
+    e12, e13, e23 = b1 == b2, b1 == b3, b2 == b3
+    e123 = e12 & e23
+    for mu in range(NCORR):
+        xk, fa, fb, fc = FACTORS[mu]
+        x = _centre_factor(xk, g1, g2, w, centers)[:, None, None, None]
+        A = _gather(mp, fa[0], fa[2], nmax, fa[1])[:, b1]      # [i, t, n2, n3]
+        B = _gather(mp, fb[0], fb[2], nmax, fb[1])[:, b2]
+        C = _gather(mp, fc[0], fc[2], nmax, fc[1])[:, b3]
+        out[mu] = np.sum(x * A * B * C, axis=0)
+        if not distinct:
+            continue
+        t12, t13, t23, t123 = TABLE1[mu]
+        c12 = _gather(mp, t12[0], t12[1], nmax)
+        c13 = _gather(mp, t13[0], t13[1], nmax)
+        c23 = _gather(mp, t23[0], t23[1], nmax)
+        t3 = _gather(mp, t123[0], t123[1], nmax)
+        out[mu][e12] -= np.sum(x * c12[:, b1[e12]] * C[:, e12], axis=0)
+        out[mu][e13] -= np.sum(x * c13[:, b1[e13]] * B[:, e13], axis=0)
+        out[mu][e23] -= np.sum(x * A[:, e23] * c23[:, b2[e23]], axis=0)
+        out[mu][e123] += 2.0 * np.sum(x * t3[:, b1[e123]], axis=0)
+    return out
+
+
+def upsilon_triplets(x, y, g1, g2, w, edges, nmax, triplets, centers=None, distinct=True,
+                     chunk=16):
+    """``upsilon`` at the listed radial-bin triplets only: complex
+    [9, ntrip, 2nmax+1, 2nmax+1], element t equal to
+    upsilon(...)[:, b1_t, b2_t, b3_t].  For bin counts whose full tensor does
+    not fit in memory (65 bins at nmax 15 is 38 GB)."""
+    x, y, g1, g2, w = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, g1, g2, w))
+    check_inputs(x, y, g1, g2, w, edges, nmax)
+    if centers is None:
+        centers = np.arange(x.size)
+    centers = np.asarray(centers, dtype=np.int64)
+    t = np.asarray(triplets, dtype=np.int64).reshape(-1, 3)
+    nb = len(edges) - 1
+    if t.size and (t.min() < 0 or t.max() >= nb):
+        raise ValueError("triplet bin out of range")
+    nn = 2 * nmax + 1
+    out = np.zeros((NCORR, len(t), nn, nn), dtype=np.complex128)
+    for s in range(0, len(centers), chunk):
+        c = centers[s:s + chunk]
+        mp = multipoles(x, y, g1, g2, w, edges, nmax, c)
+        out += contract_triplets(mp, g1, g2, w, c, nmax, t, distinct)
+    return out
+
+
 def upsilon(x, y, g1, g2, w, edges, nmax, centers=None, distinct=True,
             chunk=256):
     """The 4PCF multipoles Upsilon_{mu,(n2,n3)}(T1,T2,T3), mu = 0..7, and
@@ -332,6 +392,29 @@ def abs_bound_parallel(x, y, g1, g2, w, edges, centers, order=4, processes=1):
     chunks = np.array_split(centers, processes)
     with mp.get_context("fork").Pool(processes) as pool:
         res = pool.map(_bound_worker, [(x, y, g1, g2, w, edges, c, order) for c in chunks])
+    out = res[0]
+    for r in res[1:]:
+        out = out + r
+    return out
+
+
+def _triplet_worker(args):
+    x, y, g1, g2, w, edges, nmax, triplets, centers, distinct = args
+    return upsilon_triplets(x, y, g1, g2, w, edges, nmax, triplets, centers, distinct)
+
+
+def upsilon_triplets_parallel(x, y, g1, g2, w, edges, nmax, triplets, centers, distinct=True,
+                              processes=1):
+    """``upsilon_triplets`` over centre chunks in a process pool, added in
+    chunk order."""
+    centers = np.asarray(centers, dtype=np.int64)
+    if processes <= 1:
+        return upsilon_triplets(x, y, g1, g2, w, edges, nmax, triplets, centers, distinct)
+    import multiprocessing as mp
+    chunks = np.array_split(centers, processes)
+    with mp.get_context("fork").Pool(processes) as pool:
+        res = pool.map(_triplet_worker, [(x, y, g1, g2, w, edges, nmax, triplets, c, distinct)
+                                         for c in chunks])
     out = res[0]
     for r in res[1:]:
         out = out + r

@@ -48,7 +48,12 @@ def natural_components_triplets(ups: np.ndarray, nphi: int, triplets):
     """The conversion above for the listed radial-bin triplets (b1, b2, b3)
     only: (Gamma[8, ntrip, nphi, nphi], Nbar[ntrip, nphi, nphi])."""
     t = np.asarray(triplets, dtype=np.int64).reshape(-1, 3)
-    sel = ups[:, t[:, 0], t[:, 1], t[:, 2]]               # [9, ntrip, nn, nn]
+    return natural_components_selected(ups[:, t[:, 0], t[:, 1], t[:, 2]], nphi)
+
+
+def natural_components_selected(sel: np.ndarray, nphi: int):
+    """The same from the multipoles of the triplets alone, sel[9, ntrip,
+    2n+1, 2n+1] (as ``upsilon_triplets`` returns them)."""
     return _ratio(binned_from_multipoles(sel[:, :, None, None], nphi)[:, :, 0, 0])
 
 

@@ -185,6 +185,9 @@ def workload(name: str, ngrid: int | None = None):
                  12 log bins 1-100', nmax 10
     lognormal-10m : 2400'x2400', N=1e7 lognormal positions, 16 log bins
                  0.5-200', nmax 15
+    grf-65bin  : 600'x600', N=108000 (0.3 per arcmin^2), GRF shear as grf-1m,
+                 65 log bins 0.25-166.29', nmax 15 (the binning of the
+                 paper's mock and survey measurements, Sect. 5 and 6)
     """
     if name == "uniform-2k":
         cat = uniform_catalogue(0, 2000, 60.0)
@@ -195,6 +198,10 @@ def workload(name: str, ngrid: int | None = None):
     if name == "lognormal-10m":
         cat = lognormal_catalogue(4, 10_000_000, 2400.0, ngrid=ngrid or 4096)
         return cat, log_edges(0.5, 200.0, 16), 15, "2400'x2400' lognormal N=1e7, 16 log bins 0.5-200', nmax=15"
+    if name == "grf-65bin":
+        cat = grf_catalogue(5, 108_000, 600.0, ngrid=ngrid or 4096)
+        return (cat, log_edges(0.25, 166.29, 65), 15,
+                "600'x600' GRF N=108000, 65 log bins 0.25-166.29', nmax=15")
     raise KeyError(name)
 
 

@@ -417,3 +417,61 @@ def test_parallel_oracle_equals_serial():
     sb = oracle.abs_bound(*cat.arrays(), edges, idx)
     pb = oracle.abs_bound_parallel(*cat.arrays(), edges, idx, processes=3)
     assert np.allclose(pb, sb, rtol=1e-13, atol=0)
+
+
+# --------------------------------------------------------------------------
+# Sums at listed bin triplets (bin counts whose full tensor is too large)
+# --------------------------------------------------------------------------
+def triplet_sample(nb, seed, k):
+    """k random bin triplets plus each kind of coincident bins (b1 = b2,
+    b1 = b3, b2 = b3, all three) and the first and last bins."""
+    rng = np.random.default_rng(seed)
+    a, b = (int(v) for v in rng.choice(nb, 2, replace=False))
+    special = [(a, a, b), (a, b, a), (b, a, a), (a, a, a), (0, 0, 0), (nb - 1, nb - 1, nb - 1),
+               (0, nb - 1, nb - 1), (nb - 1, 0, nb - 1)]
+    return np.concatenate([rng.integers(0, nb, size=(k, 3)), np.array(special)])
+
+
+@pytest.mark.parametrize("distinct", [False, True])
+def test_triplet_sums_equal_brute_force(distinct):
+    """20 radial bins, nmax 2: the sums at listed triplets against the
+    quadruplet enumeration of the definition, at random and coincident bins
+    (every coincidence kind present with non-zero values)."""
+    cat = tiny(11, n=40, side=12.0)
+    nb = 20
+    edges = synth.log_edges(0.4, 9.0, nb)
+    t = triplet_sample(nb, 5, 60)
+    # the bins holding most pairs, so that the coincident triplets are not empty
+    cnt = oracle.bin_counts(cat[0], cat[1], edges, np.arange(40)).sum(axis=0)
+    p, q = (int(v) for v in np.argsort(cnt)[-2:])
+    t = np.concatenate([t, [(p, p, q), (p, q, p), (q, p, p), (p, p, p), (p, q, q)]])
+    a = oracle.upsilon_triplets(*cat, edges, 2, t, distinct=distinct)
+    full = oracle.brute_upsilon(*cat, edges, 2, distinct=distinct).reshape(9, nb, nb, nb, 5, 5)
+    b = full[:, t[:, 0], t[:, 1], t[:, 2]]
+    for k in range(len(t) - 5, len(t)):
+        assert np.abs(b[:, k]).max() > 0
+    assert np.all(rel(a, b) < 1e-12)
+
+
+def test_triplet_sums_equal_full_tensor():
+    """33 bins, nmax 3, 40 centres of the uniform 2000-galaxy catalogue: the
+    triplet sums equal the corresponding elements of the full tensor."""
+    cat, _, _, _ = synth.workload("uniform-2k")
+    nb = 33
+    edges = synth.log_edges(1.0, 30.0, nb)
+    idx = np.random.default_rng(8).choice(cat.n, 40, replace=False)
+    full = oracle.upsilon(*cat.arrays(), edges, 3, centers=idx)
+    t = triplet_sample(nb, 9, 200)
+    a = oracle.upsilon_triplets(*cat.arrays(), edges, 3, t, centers=idx)
+    b = full[:, t[:, 0], t[:, 1], t[:, 2]]
+    assert np.abs(b).max() > 0
+    assert np.all(rel(a, b) < 1e-13)
+    g1, n1 = oracle.natural_components_triplets(full, 17, t)
+    g2, n2 = oracle.natural_components_selected(a, 17)
+    assert np.linalg.norm(n1 - n2) <= 1e-12 * np.linalg.norm(n1)
+    # Gamma = Ubar / Nbar: compared where Nbar is not a rounding residue of an
+    # empty angular bin
+    ok = np.abs(n1) > 1e-8 * np.abs(n1).max()
+    assert np.linalg.norm((g1 - g2)[:, ok]) <= 1e-12 * np.linalg.norm(g1[:, ok])
+    par = oracle.upsilon_triplets_parallel(*cat.arrays(), edges, 3, t, idx, processes=2)
+    assert np.all(rel(par, a) < 1e-14)
