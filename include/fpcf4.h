@@ -71,7 +71,7 @@ enum { FPCF4_MEM_HOST = 0, FPCF4_MEM_DEVICE = 1 };
 enum { FPCF4_FP64 = 0, FPCF4_MIXED_FP16 = 1, FPCF4_MIXED_BF16 = 2 };
 
 #define FPCF4_NMAX_SUPPORTED 16   /* largest nmax compiled in              */
-#define FPCF4_NBINS_SUPPORTED 16  /* largest number of radial bins         */
+#define FPCF4_NBINS_SUPPORTED 128 /* largest number of radial bins         */
 #define FPCF4_NMAX3_SUPPORTED 32  /* largest 3PCF multipole (2 x the above) */
 #define FPCF4_NCORR 9             /* Upsilon_0..7 and N                    */
 

@@ -12,7 +12,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 FP64, MIXED_FP16, MIXED_BF16 = 0, 1, 2
 NMAX_SUPPORTED = 16
 NMAX3_SUPPORTED = 32
-NBINS_SUPPORTED = 16
+NBINS_SUPPORTED = 128
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 STATUS_NAMES = {

@@ -56,6 +56,14 @@ inline size_t up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
 
 // Default centre tile: records of one tile stay below this many bytes.
 constexpr size_t kTileRecordBudget = size_t(32) << 30;
+// Centre slices of the pair contraction each own a binary64 partial of all
+// work items; their number is cut so the partials stay below this many bytes
+// (one slice at least: at 65 bins and nmax 15 one slice is about 21 GB).
+constexpr size_t kPairPartialBudget = size_t(48) << 30;
+// Scheduling counters of stage (a) (8 per launch, two launches), then the
+// per-bin scaling maxima.
+constexpr int kSchedCounters = 128;
+constexpr int kCounterWords = kSchedCounters + MAXIMA_WORDS;
 
 struct PlanInfo {
   int64_t n = 0, ncent = 0, tile = 0, ntiles = 0, ldc = 0;
@@ -153,7 +161,7 @@ fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   if (tile <= 0) tile = (int64_t)(kTileRecordBudget / rec_per_centre);
   if (tile > P.ncent) tile = P.ncent;
   if (tile < 1) tile = 1;
-  if (tile > (int64_t(1) << 30)) tile = int64_t(1) << 30;
+  if (tile > (int64_t(1) << 29)) tile = int64_t(1) << 29;   // 4 work-items per centre in the relayout grid < 2^32
   P.tile = tile;
   P.ldc = (tile + 15) / 16 * 16;
   P.ntiles = P.ncent > 0 ? (P.ncent + tile - 1) / tile : 0;
@@ -169,7 +177,7 @@ fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   P.o_centres = take((size_t)std::max<int64_t>(P.ncent, 1) * 4);
   P.o_e2 = take((P.nb + 1) * 8);
   P.o_edges = take((P.nb + 1) * 8);
-  P.o_counters = take(256 * 4);   // 128 scheduling counters + 64 scaling maxima
+  P.o_counters = take(kCounterWords * 4);   // scheduling counters, then the scaling maxima
   P.o_bbox = take(4 * 8);
   P.o_bad = take(16);
   P.o_pairs = take(16);
@@ -186,7 +194,9 @@ fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
         return fail(FPCF4_E_DEVICE, "internal: contraction plan leaves an output unassigned");
     P.pitems = (int64_t)pp.items.size();
     P.prows = pp.total_rows;
-    P.pslices = pair_slices(P.tile);
+    const size_t slice_bytes = (size_t)P.prows * P.nb * P.nb * 8;
+    const int64_t fit = std::max<int64_t>(1, (int64_t)(kPairPartialBudget / std::max<size_t>(slice_bytes, 1)));
+    P.pslices = (int)std::min<int64_t>(pair_slices(P.tile), fit);
   }
   P.o_pitems = take((size_t)P.pitems * sizeof(PairItem));
   P.o_pout = take(pairs ? (size_t)FPCF4_NCORR * nn * nn * sizeof(PairOut) : 0);
@@ -421,7 +431,8 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
     for (auto e : evs) R->ev.push_back(e);
     HIPCHK(hipEventRecord(evs[0], s));
   }
-  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(256), 0, s, counters, 256);
+  hipLaunchKernelGGL(zero_kernel, dim3((kCounterWords + 255) / 256), dim3(256), 0, s, counters,
+                     kCounterWords);
   HIPCHK(hipGetLastError());
   StageAArgs a{};
   a.cat.n = P.n;
@@ -434,7 +445,7 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
   a.ldc = (int32_t)P.ldc;
   a.xg = R->ws + P.o_xg;
   a.xw = R->ws + P.o_xw;
-  a.maxima = P.precision == FPCF4_FP64 ? nullptr : reinterpret_cast<unsigned*>(counters + 128);
+  a.maxima = P.precision == FPCF4_FP64 ? nullptr : reinterpret_cast<unsigned*>(counters + kSchedCounters);
   a.e2 = R->at<double>(P.o_e2);
   a.edges = R->at<double>(P.o_edges);
   a.rec = R->ws + P.o_region;
@@ -442,7 +453,8 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
   a.counts = R->want_counts ? R->at<int32_t>(P.o_counts) : nullptr;
   a.work_counter = counters;
   a.pairs = R->at<unsigned long long>(P.o_pairs);
-  a.bin_mask = (P.nb >= 32) ? 0xffffffffu : ((1u << P.nb) - 1u);
+  a.b_lo = 0;
+  a.b_hi = P.nb;
   for (int b = 0; b < P.nb; ++b) a.level[b] = P.level[b];
   for (int d = 1; d <= P.tree_levels; ++d) {
     a.rgal[d - 1] = R->ws + P.o_rgal[d - 1];
@@ -482,6 +494,7 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
     pl.nb = P.nb;
     pl.nmax = P.nmax;
     pl.precision = P.precision;
+    pl.max_slices = P.pslices;
     pl.part = R->at<double>(P.o_ppart);
     pl.total_rows = P.prows;
     pl.ups = R->at<double>(P.o_ups);

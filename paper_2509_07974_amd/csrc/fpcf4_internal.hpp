@@ -96,6 +96,26 @@ template <> struct alignas(16) GalR<float> {
 static_assert(sizeof(GalR<float>) == 64, "pseudo-galaxy record size");
 constexpr int TREE_LEVELS_MAX = 4;
 
+// Per-bin maxima of the records of a tile, written by stage (a) and read by
+// the mixed-precision contraction to pick its power-of-two operand scales:
+// float bits (all values are >= 0, so unsigned max is float max).
+constexpr int MAXIMA_G = 0;                              // [nb] max |G_k| component per bin
+constexpr int MAXIMA_W = FPCF4_NBINS_SUPPORTED;          // [nb] max |W_k| component per bin
+constexpr int MAXIMA_X = 2 * FPCF4_NBINS_SUPPORTED;      // +0: max |w g| component, +1: max |w|
+constexpr int MAXIMA_WORDS = 2 * FPCF4_NBINS_SUPPORTED + 2;
+
+// Bin tiles of the contraction kernels: each workgroup holds at most
+// BIN_TILE_MAX radial bins per bin dimension, so nb bins are cut into nt
+// near-equal tiles of at most tb bins (one tile when nb <= BIN_TILE_MAX).
+constexpr int BIN_TILE_MAX = 16;
+struct BinTiles {
+  int tb, nt;
+};
+__host__ __device__ inline BinTiles bin_tiles(int nb) {
+  const int nt = (nb + BIN_TILE_MAX - 1) / BIN_TILE_MAX;
+  return BinTiles{nt > 0 ? (nb + nt - 1) / nt : 0, nt};
+}
+
 // Sorted catalogue on the device.
 struct SortedCat {
   int64_t n;
@@ -116,11 +136,11 @@ struct StageAArgs {
   void* rec_aos;            // staging [centre][bin][entry] complex (T)
   void* xg;                 // [ldc] complex (T): w g of each tile centre
   void* xw;                 // [ldc] (T): w of each tile centre
-  unsigned* maxima;         // fp16 scaling maxima (float bits) or null
+  unsigned* maxima;         // scaling maxima (float bits, MAXIMA_* layout) or null
   int32_t* counts;          // [ncent][nb] or null
   int32_t* work_counter;    // dynamic centre scheduling counters, one per XCD
   unsigned long long* pairs;  // in-bin pair counter (may be null)
-  uint32_t bin_mask;        // bins to accumulate (bit b); the rest are left alone
+  int32_t b_lo, b_hi;       // bins to accumulate: [b_lo, b_hi); the rest are left alone
   // tree approximation: bins with level[b] = d >= 1 take their neighbours
   // from reduced catalogue d (same search grid as cat); 0 = discrete
   int8_t level[FPCF4_NBINS_SUPPORTED];
@@ -194,6 +214,7 @@ struct PairArgs {
   const unsigned* maxima;
   const PairItem* items;
   int32_t item0, nitems, ncent, nb, nmax;
+  int32_t tb, nt;                  // bin tiles (bin_tiles(nb)); blockIdx.z = (t1 nt + t2) nt + t3
   double* part;                    // [slices][total_rows][nb^2]
   int64_t total_rows;
 };
@@ -207,6 +228,7 @@ struct PairLaunch {
   const PairOut* out;
   int cls_start[PAIR_MAX_BLK + 1], cls_count[PAIR_MAX_BLK + 1];
   int ncent, nb, nmax, precision;
+  int max_slices;                  // centre slices the partial buffer holds
   double* part;
   int64_t total_rows;
   double* ups;                     // accumulated into

@@ -495,6 +495,9 @@ template <typename T, int W, int NMX, bool RED> struct Shared {
   int rows[2][5][64];       // row table: s1, l1, s2, row length, inclusive prefix
   int cnt[W];               // in-bin count of each wave's chunk in this round
   int cent[2];              // centre broadcast
+  // per-bin record maxima of the workgroup (G, W), float bits; binary32
+  // records only (the binary64 path does not scale its operands)
+  unsigned bmax[2][sizeof(T) == 4 ? FPCF4_NBINS_SUPPORTED : 1];
 };
 
 // First powers z^K0 of passes P..W-1, each the previous one times
@@ -586,8 +589,12 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
   unsigned tc = 0;     // centres so far (broadcast-slot parity)
   unsigned tt = 0;     // row tables so far (table parity)
   unsigned long long wave_pairs = 0;
-  float lane_gmax = 0.f, lane_wmax = 0.f;   // lane b: maxima of bin b
   float lane_xmax = 0.f, lane_wxmax = 0.f;  // lane 0: |w g| and |w| maxima
+  if constexpr (sizeof(T) == 4) {
+    // cleared before the first barrier of the centre loop orders it
+    for (int q = (int)threadIdx.x; q < 2 * FPCF4_NBINS_SUPPORTED; q += (int)blockDim.x)
+      sh.bmax[q / FPCF4_NBINS_SUPPORTED][q % FPCF4_NBINS_SUPPORTED] = 0u;
+  }
 
   for (;;) {
     if constexpr (P0) {
@@ -628,9 +635,8 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
       }
     }
 
-    for (int b = 0; b < nb; ++b) {
-      // bins of the other launch (discrete / reduced catalogues) are skipped
-      if (((a.bin_mask >> b) & 1u) == 0u) continue;
+    // the launch's bins (discrete or reduced catalogues); the others are left alone
+    for (int b = a.b_lo; b < a.b_hi; ++b) {
       const Rec* __restrict__ ngal = reinterpret_cast<const Rec*>(RED ? a.rgal[a.level[b] - 1] : a.cat.gal);
       const int32_t* __restrict__ cstart = RED ? a.rcell[a.level[b] - 1] : a.cat.cell_start;
       const double e2lo = a.e2[b], e2hi = a.e2[b + 1];
@@ -901,15 +907,17 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
           else if (e < L.offQ) wmax = fmaxf(wmax, mx);
         }
       }
-      if (a.maxima != nullptr) {
+      if constexpr (sizeof(T) == 4) {
+        if (a.maxima != nullptr) {
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-          gmax = fmaxf(gmax, __shfl_xor(gmax, d, 64));
-          wmax = fmaxf(wmax, __shfl_xor(wmax, d, 64));
-        }
-        if ((int)lane == b) {
-          lane_gmax = fmaxf(lane_gmax, gmax);
-          lane_wmax = fmaxf(lane_wmax, wmax);
+          for (int d = 32; d >= 1; d >>= 1) {
+            gmax = fmaxf(gmax, __shfl_xor(gmax, d, 64));
+            wmax = fmaxf(wmax, __shfl_xor(wmax, d, 64));
+          }
+          if (lane == 0) {
+            atomicMax(&sh.bmax[0][b], __float_as_uint(gmax));
+            atomicMax(&sh.bmax[1][b], __float_as_uint(wmax));
+          }
         }
       }
       if (P0) {
@@ -920,14 +928,18 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
     }
   }
   if (P0 && a.pairs != nullptr && lane == 0 && wave_pairs) atomicAdd(a.pairs, wave_pairs);
-  if (a.maxima != nullptr) {
-    if ((int)lane < nb) {
-      atomicMax(a.maxima + lane, __float_as_uint(lane_gmax));
-      atomicMax(a.maxima + 16 + lane, __float_as_uint(lane_wmax));
-    }
-    if (P0 && lane == 0) {
-      atomicMax(a.maxima + 32, __float_as_uint(lane_xmax));
-      atomicMax(a.maxima + 33, __float_as_uint(lane_wxmax));
+  if constexpr (sizeof(T) == 4) {
+    if (a.maxima != nullptr) {
+      // every wave left the centre loop after the same barrier, so the
+      // workgroup's LDS maxima are complete
+      for (int q = (int)threadIdx.x; q < nb; q += (int)blockDim.x) {
+        atomicMax(a.maxima + MAXIMA_G + q, sh.bmax[0][q]);
+        atomicMax(a.maxima + MAXIMA_W + q, sh.bmax[1][q]);
+      }
+      if (P0 && lane == 0) {
+        atomicMax(a.maxima + MAXIMA_X, __float_as_uint(lane_xmax));
+        atomicMax(a.maxima + MAXIMA_X + 1, __float_as_uint(lane_wxmax));
+      }
     }
   }
 }
@@ -942,7 +954,7 @@ __device__ __forceinline__ void dispatch(int wv, const StageAArgs& a,
 }
 
 // RED: neighbours from the reduced catalogues of the tree approximation
-// (binary32 only); the launch accumulates the bins of a.bin_mask.
+// (binary32 only); the launch accumulates the bins [a.b_lo, a.b_hi).
 template <typename T, int N, bool RED>
 __global__ __launch_bounds__((64 * Conf<T, N>::W)) __attribute__((amdgpu_waves_per_eu(Conf<T, N>::EU))) void stage_a_kernel(StageAArgs a) {
   __shared__ Shared<T, Conf<T, N>::W, Conf<T, N>::NMX, RED> sh;
@@ -1020,22 +1032,22 @@ static hipError_t launch_pairs(const StageAArgs& a, hipStream_t s) {
 // scheduling counters); then the relayout of all records.
 template <typename T, int N>
 hipError_t launch_n(const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t mid) {
-  uint32_t exact = 0, red = 0;
-  for (int b = 0; b < a.nb; ++b) {
-    if (!((a.bin_mask >> b) & 1u)) continue;
-    if (a.level[b] > 0) red |= 1u << b;
-    else exact |= 1u << b;
-  }
+  // the level of a bin never decreases with its radius, so the discrete bins
+  // are a prefix of [b_lo, b_hi) and the reduced ones the rest
+  int k = a.b_lo;
+  while (k < a.b_hi && a.level[k] == 0) ++k;
+  for (int b = k; b < a.b_hi; ++b)
+    if (a.level[b] == 0) return hipErrorInvalidValue;
+  const bool red = k < a.b_hi;
+  StageAArgs ae = a, ar = a;
+  ae.b_hi = k;
+  ar.b_lo = k;
   *nlaunch = 0;
-  StageAArgs ae = a;
-  ae.bin_mask = exact;
   hipError_t e = launch_pairs<T, N, false>(ae, s);
   if (e != hipSuccess) return e;
   *nlaunch = 1;
   if (red) {
     if constexpr (sizeof(T) == 4 && !is3(N)) {
-      StageAArgs ar = a;
-      ar.bin_mask = red;
       ar.work_counter = a.work_counter + 8;
       if ((e = launch_pairs<T, N, true>(ar, s)) != hipSuccess) return e;
       *nlaunch = 2;

@@ -72,6 +72,13 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   const int nch_all = (ncent + CKC - 1) / CKC;
   const int ch0 = (int)(((int64_t)nch_all * blockIdx.y) / gridDim.y);
   const int ch1 = (int)(((int64_t)nch_all * (blockIdx.y + 1)) / gridDim.y);
+  // bin tile (blockIdx.z = te nt + tf): equal-bin rows b_eq in [oe, oe + ne),
+  // other-factor columns b' in [of, of + nf); the triple term has one column
+  const BinTiles bt = bin_tiles(nb);
+  const int te = (int)blockIdx.z / bt.nt, tf = (int)blockIdx.z % bt.nt;
+  if (kind == 3 && tf != 0) return;
+  const int oe = te * bt.tb, of = tf * bt.tb;
+  const int ne = imin(bt.tb, nb - oe), nf = imin(bt.tb, nb - of);
 
   __shared__ cplx Es[2][16][CKC + 1];
   __shared__ cplx Fs[2][16][CKC + 1];
@@ -98,10 +105,11 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int b = (tid + 256 * h) / CKC;
-    slot_ok[h] = b < nb;
-    const int bb = slot_ok[h] ? b : 0;
-    pe_row[h] = rec + 2 * (((int64_t)eidx * nb + bb) * a.ldc);
-    pf_row[h] = rec + 2 * (((int64_t)e_fo * nb + bb) * a.ldc);
+    // a slot past ne (nf) loads a clamped row that is never read
+    slot_ok[h] = b < ne || b < nf;
+    const int be = b < ne ? b : 0, bf = b < nf ? b : 0;
+    pe_row[h] = rec + 2 * (((int64_t)eidx * nb + oe + be) * a.ldc);
+    pf_row[h] = rec + 2 * (((int64_t)e_fo * nb + of + bf) * a.ldc);
   }
   const double fone = 1.0;   // kind 3: F = 1 in column 0
 
@@ -154,12 +162,12 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
     const int row = 16 * m + (lane & 15);
-    rok[m] = row < 2 * nb;
-    rp[m] = rok[m] ? row / nb : 0;
-    rb[m] = rok[m] ? row % nb : 0;
+    rok[m] = row < 2 * ne;
+    rp[m] = rok[m] ? row / ne : 0;
+    rb[m] = rok[m] ? row % ne : 0;
   }
   const int col = lane & 15;
-  const bool cok = col < nb;
+  const bool cok = col < nf;
   const int kq = lane >> 4;   // K index within the 4-wide step: centre kq/2, part kq%2
   d4 acc[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
 
@@ -207,8 +215,8 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int row = 16 * m + 4 * e + (lane >> 4);   // f64 D layout
-      if (row >= 2 * nb || !cok || (kind == 3 && col != 0)) continue;
-      const int part = row / nb, beq = row % nb, bo = col;
+      if (row >= 2 * ne || !cok || (kind == 3 && col != 0)) continue;
+      const int part = row / ne, beq = oe + row % ne, bo = of + col;
       int64_t o;
       if (kind == 0) o = ((int64_t)beq * nb + bo) * nn + (ord + n);
       else if (kind == 1) o = (int64_t)nb * nb * nn + ((int64_t)beq * nb + bo) * nn + (ord + n);
@@ -234,7 +242,8 @@ hipError_t launch_corrections(const CorrArgs& a, hipStream_t s) {
   if (a.ncent <= 0) return hipSuccess;
   const int nn = 2 * a.nmax + 1, ns = 4 * a.nmax + 1;
   const int blocks = 9 * (2 * nn + ns + 1);
-  hipLaunchKernelGGL(corr_kernel<T>, dim3(blocks, CORR_SLICES), dim3(256), 0, s, a);
+  const BinTiles bt = bin_tiles(a.nb);
+  hipLaunchKernelGGL(corr_kernel<T>, dim3(blocks, CORR_SLICES, bt.nt * bt.nt), dim3(256), 0, s, a);
   const int64_t elems = 2 * (int64_t)corr_elems(a.nb, a.nmax);
   hipLaunchKernelGGL(corr_reduce_kernel, dim3((int)((elems + 255) / 256)), dim3(256), 0, s,
                      (const double*)a.part, elems, a.corr);

@@ -40,6 +40,7 @@
 // same lanes read back what they wrote).  pair_reduce_kernel adds the slices
 // in order and scatters every (mu, n2, n3) from its item and orientation into
 // the output tensor.  No atomics: the result is deterministic.
+#include <algorithm>
 #include <map>
 #include <tuple>
 #include <type_traits>
@@ -212,6 +213,24 @@ __device__ __forceinline__ int rec_entry(const Layout& L, int fam, int k) {
   return fam == F_G ? eG(L, k) : eW(L, k);
 }
 
+// The bin tile of this workgroup (blockIdx.z = (t1 nt + t2) nt + t3): the
+// bins b1, b2, b3 it covers are [o, o + n) with n <= tb.
+struct BinRange {
+  int o1, o2, o3, n1, n2, n3;
+};
+__device__ __forceinline__ BinRange bin_range(const PairArgs& a) {
+  const int z = (int)blockIdx.z, nt = a.nt, tb = a.tb;
+  const int t3 = z % nt, t2 = (z / nt) % nt, t1 = z / (nt * nt);
+  BinRange r;
+  r.o1 = t1 * tb;
+  r.o2 = t2 * tb;
+  r.o3 = t3 * tb;
+  r.n1 = imin(tb, a.nb - r.o1);
+  r.n2 = imin(tb, a.nb - r.o2);
+  r.n3 = imin(tb, a.nb - r.o3);
+  return r;
+}
+
 // The hardware deals workgroups to the 8 XCDs round-robin in dispatch order.
 // Renumber them so that each XCD runs a contiguous range of (slice, item):
 // the items of one centre slice, which read the same record columns, then
@@ -246,9 +265,12 @@ void contract_pair_kernel(PairArgs a) {
   const PairItem it = a.items[a.item0 + bx];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int ncols = nb * nb;
+  // bin tile: b1 in [o1, o1 + n1), b2 in [o2, o2 + n2), b3 in [o3, o3 + n3)
+  const BinRange br = bin_range(a);
+  const int o1 = br.o1, o2 = br.o2, o3 = br.o3, n1 = br.n1, n2 = br.n2, n3 = br.n3;
+  const int ncols = n2 * n3;              // columns (b2, b3) of the tile
   const int ntiles = (ncols + 15) >> 4;
-  const int mrows = NBLK * 2 * nb;
+  const int mrows = NBLK * 2 * n1;
   // centres [cbase, cbase + ncent) of this slice
   const int per = (int)((((int64_t)a.ncent + gridDim.y - 1) / gridDim.y + PKC - 1) / PKC * PKC);
   const int cbase = by * per;
@@ -265,14 +287,14 @@ void contract_pair_kernel(PairArgs a) {
   if (tid < 16) {
     const unsigned* M = a.maxima;
     float sy = 1.0f, sb = 1.0f, sc = 1.0f;
-    if (tid < nb) {
-      const int famA = it.blk[0].fam == F_G ? 0 : 16;
-      const float mx = __uint_as_float(M[it.blk[0].x == X_W ? 33 : 32]);
-      // y = x A below 2^14 per component, B and C below 2^6: R = B C below 2^13
-      sy = pow2_under(2.0f * mx * __uint_as_float(M[famA + tid]), 14);
-      sb = pow2_under(1.5f * __uint_as_float(M[(it.famB == F_G ? 0 : 16) + tid]), 6);
-      sc = pow2_under(1.5f * __uint_as_float(M[(it.famC == F_G ? 0 : 16) + tid]), 6);
+    // y = x A below 2^14 per component, B and C below 2^6: R = B C below 2^13
+    if (tid < n1) {
+      const int famA = it.blk[0].fam == F_G ? MAXIMA_G : MAXIMA_W;
+      const float mx = __uint_as_float(M[MAXIMA_X + (it.blk[0].x == X_W ? 1 : 0)]);
+      sy = pow2_under(2.0f * mx * __uint_as_float(M[famA + o1 + tid]), 14);
     }
+    if (tid < n2) sb = pow2_under(1.5f * __uint_as_float(M[(it.famB == F_G ? MAXIMA_G : MAXIMA_W) + o2 + tid]), 6);
+    if (tid < n3) sc = pow2_under(1.5f * __uint_as_float(M[(it.famC == F_G ? MAXIMA_G : MAXIMA_W) + o3 + tid]), 6);
     scl[0][tid] = sy; inv[0][tid] = 1.0f / sy;
     scl[1][tid] = sb; inv[1][tid] = 1.0f / sb;
     scl[2][tid] = sc; inv[2][tid] = 1.0f / sc;
@@ -290,10 +312,10 @@ void contract_pair_kernel(PairArgs a) {
   // ---- staging slots of this thread (one each)
   // B / C: a pair of centres 2p, 2p+1 of bin sb, loaded as 16 bytes
   const int sbin = tid >> 4, spair = tid & 15;
-  const bool s_on = sbin < nb;
+  const bool sb_on = sbin < n2, sc_on = sbin < n3;
   const float* recf = reinterpret_cast<const float*>(a.rec);
-  const float* rowBp = recf + 2 * (((int64_t)rec_entry(L, it.famB, it.ordB) * nb + (s_on ? sbin : 0)) * ldc);
-  const float* rowCp = recf + 2 * (((int64_t)rec_entry(L, it.famC, it.ordC) * nb + (s_on ? sbin : 0)) * ldc);
+  const float* rowBp = recf + 2 * (((int64_t)rec_entry(L, it.famB, it.ordB) * nb + o2 + (sb_on ? sbin : 0)) * ldc);
+  const float* rowCp = recf + 2 * (((int64_t)rec_entry(L, it.famC, it.ordC) * nb + o3 + (sc_on ? sbin : 0)) * ldc);
   // left operand: unit (block, b1, K-step, lane group q) = four consecutive
   // centres 16 ks + 4 q + (0..3) of row (block, b1); it writes the
   // real-output and the imaginary-output rows of that b1
@@ -301,10 +323,10 @@ void contract_pair_kernel(PairArgs a) {
   // consecutive 16-byte slots of the operand (no LDS bank conflicts)
   const int ub1 = tid % NBC, urest = tid / NBC;
   const int uq = urest & 3, uks = (urest >> 2) & 1, ublk = urest >> 3;
-  const bool u_on = ublk < NBLK && ub1 < nb;
+  const bool u_on = ublk < NBLK && ub1 < n1;
   PairRow rb = it.blk[0];
   if (NBLK > 1 && ublk == 1) rb = it.blk[1];
-  const float* rowAp = recf + 2 * (((int64_t)rec_entry(L, rb.fam, rb.order) * nb + (u_on ? ub1 : 0)) * ldc);
+  const float* rowAp = recf + 2 * (((int64_t)rec_entry(L, rb.fam, rb.order) * nb + o1 + (u_on ? ub1 : 0)) * ldc);
   const bool xconj = rb.x == X_GC, aconj = rb.conj != 0;
   const bool x_is_w = it.blk[0].x == X_W;   // the W items use w; all others w g
   const float4* xg4 = reinterpret_cast<const float4*>(a.xg);
@@ -327,9 +349,10 @@ void contract_pair_kernel(PairArgs a) {
     }
   };
   auto commit = [&](int c0, int buf) {
-    if (s_on) {
+    if (sb_on || sc_on) {
       // centres past the tile read stale record memory (possibly NaN
-      // patterns) inside the row stride: select zeros, never multiply
+      // patterns) inside the row stride: select zeros, never multiply.
+      // (A row past n2 or n3 holds a clamped bin and is never read.)
       const int cc = 2 * spair;
       const bool l0 = c0 + cc < ncent, l1 = c0 + cc + 1 < ncent;
       const float sb = scl[1][sbin], sc = scl[2][sbin];
@@ -370,7 +393,7 @@ void contract_pair_kernel(PairArgs a) {
       H8 hr, lr, hi, li;
       split8<PREC>(vr, hr, lr);
       split8<PREC>(vi, hi, li);
-      const int r_re = ublk * 2 * nb + ub1, r_im = r_re + nb;
+      const int r_re = ublk * 2 * n1 + ub1, r_im = r_re + n1;
       Ys[buf][uks][r_re >> 4][0][16 * uq + (r_re & 15)] = hr;
       Ys[buf][uks][r_re >> 4][1][16 * uq + (r_re & 15)] = lr;
       Ys[buf][uks][r_im >> 4][0][16 * uq + (r_im & 15)] = hi;
@@ -389,8 +412,8 @@ void contract_pair_kernel(PairArgs a) {
   for (int t = 0; t < NT; ++t) {
     const int j = 16 * (wr + W * t) + (lane & 15);
     colok[t] = t < ntw && j < ncols;
-    b2c[t] = colok[t] ? j / nb : 0;
-    b3c[t] = colok[t] ? j % nb : 0;
+    b2c[t] = colok[t] ? j / n3 : 0;
+    b3c[t] = colok[t] ? j % n3 : 0;
   }
 
   f4 acc[MT][NT], mid[MT][NT];
@@ -444,7 +467,10 @@ void contract_pair_kernel(PairArgs a) {
 
   // write (first) or add the running sum, unscaled (exact powers of two), into
   // this workgroup's region of the slice partial buffer, then clear it
-  double* part = a.part + ((int64_t)by * a.total_rows + it.row0) * ncols;
+  // the item's region holds rows (block, re/im, b1) x columns (b2, b3) over
+  // all nb bins; this workgroup owns the tile's rows and columns in it
+  const int64_t gcols = (int64_t)nb * nb;
+  double* part = a.part + ((int64_t)by * a.total_rows + it.row0) * gcols;
   auto flush = [&](bool first) {
     // opaque to the optimiser: the flush runs once per 8192 centres, so its
     // addresses are recomputed there instead of being hoisted out of the
@@ -456,18 +482,21 @@ void contract_pair_kernel(PairArgs a) {
     for (int t = 0; t < NT; ++t) {
       if (colok[t]) {
         const int j = 16 * (wr + W * t) + (ln & 15);
-        const int b2 = j / nb, b3 = j - b2 * nb;
+        const int b2 = j / n3, b3 = j - b2 * n3;
         const float ubc = inv[1][b2] * inv[2][b3];
+        const int64_t gj = (int64_t)(o2 + b2) * nb + o3 + b3;
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = 16 * m + 4 * (ln >> 4) + r;
             if (row < mrows) {
-              // b1 = row mod nb (row < 4 nb)
-              const int b1 = row - nb * ((row >= nb) + (row >= 2 * nb) + (row >= 3 * nb));
+              // row = k n1 + b1 with k = 2 block + (re/im) < 4; in the item's
+              // region that row sits at k nb + o1 + b1
+              const int k = (row >= n1) + (row >= 2 * n1) + (row >= 3 * n1);
+              const int b1 = row - k * n1;
               const double v = (double)mid[m][t][r] * (double)ubc * (double)inv[0][b1];
-              double* p = pbase + (int64_t)row * ncols + j;
+              double* p = pbase + (int64_t)(k * nb + o1 + b1) * gcols + gj;
               *p = first ? v : *p + v;
             }
           }
@@ -542,9 +571,11 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_f64_
   const PairItem it = a.items[a.item0 + bx];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int ncols = nb * nb;
+  const BinRange br = bin_range(a);
+  const int o1 = br.o1, o2 = br.o2, o3 = br.o3, n1 = br.n1, n2 = br.n2, n3 = br.n3;
+  const int ncols = n2 * n3;
   const int ntiles = (ncols + 15) >> 4;
-  const int mrows = NBLK * 2 * nb;
+  const int mrows = NBLK * 2 * n1;
   const int per = (int)((((int64_t)a.ncent + gridDim.y - 1) / gridDim.y + PKC - 1) / PKC * PKC);
   const int cbase = by * per;
   const int ncent = imax(0, imin(a.ncent - cbase, per));
@@ -558,14 +589,14 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_f64_
   // staging slots: B / C pair of centres 2p, 2p+1 of bin sbin; left-operand
   // unit (block, b1, group of 4 centres)
   const int sbin = tid >> 4, spair = tid & 15;
-  const bool s_on = sbin < nb;
-  const double* rowBp = rec + 2 * (((int64_t)rec_entry(L, it.famB, it.ordB) * nb + (s_on ? sbin : 0)) * ldc);
-  const double* rowCp = rec + 2 * (((int64_t)rec_entry(L, it.famC, it.ordC) * nb + (s_on ? sbin : 0)) * ldc);
+  const bool sb_on = sbin < n2, sc_on = sbin < n3;
+  const double* rowBp = rec + 2 * (((int64_t)rec_entry(L, it.famB, it.ordB) * nb + o2 + (sb_on ? sbin : 0)) * ldc);
+  const double* rowCp = rec + 2 * (((int64_t)rec_entry(L, it.famC, it.ordC) * nb + o3 + (sc_on ? sbin : 0)) * ldc);
   const int ug = tid & 7, ub1 = (tid >> 3) % NBC, ublk = (tid >> 3) / NBC;
-  const bool u_on = ublk < NBLK && ub1 < nb;
+  const bool u_on = ublk < NBLK && ub1 < n1;
   PairRow rb = it.blk[0];
   if (NBLK > 1 && ublk == 1) rb = it.blk[1];
-  const double* rowAp = rec + 2 * (((int64_t)rec_entry(L, rb.fam, rb.order) * nb + (u_on ? ub1 : 0)) * ldc);
+  const double* rowAp = rec + 2 * (((int64_t)rec_entry(L, rb.fam, rb.order) * nb + o1 + (u_on ? ub1 : 0)) * ldc);
   const bool xconj = rb.x == X_GC, aconj = rb.conj != 0;
   const bool x_is_w = it.blk[0].x == X_W;
   const double* xg = reinterpret_cast<const double*>(a.xg);
@@ -588,7 +619,7 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_f64_
     }
   };
   auto commit = [&](int c0, int buf) {
-    if (s_on) {
+    if (sb_on || sc_on) {   // a row past n2 or n3 holds a clamped bin and is never read
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
         const bool live = c0 + 2 * spair + v < ncent;   // past the tile: stale memory, select zeros
@@ -617,8 +648,8 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_f64_
   for (int t = 0; t < NT; ++t) {
     const int j = 16 * (wr + W * t) + (lane & 15);
     colok[t] = t < ntw && j < ncols;
-    b2c[t] = colok[t] ? j / nb : 0;
-    b3c[t] = colok[t] ? j % nb : 0;
+    b2c[t] = colok[t] ? j / n3 : 0;
+    b3c[t] = colok[t] ? j % n3 : 0;
   }
   // this lane's left-operand row in each row tile: (block, re/im, b1)
   int rblk[MT], rb1[MT];
@@ -628,9 +659,9 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_f64_
     const int r = 16 * m + (lane & 15);
     rok[m] = r < mrows;
     const int rr = rok[m] ? r : 0;
-    rblk[m] = rr / (2 * nb);
-    rpart[m] = (rr % (2 * nb)) >= nb;
-    rb1[m] = rr % nb;
+    rblk[m] = rr / (2 * n1);
+    rpart[m] = (rr % (2 * n1)) >= n1;
+    rb1[m] = rr % n1;
   }
   d4 acc[MT][NT];
 #pragma unroll
@@ -673,17 +704,25 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_f64_
     __syncthreads();
   }
   // f64 D layout: element r of lane L is row 4 r + L / 16, column L % 16
-  double* part = a.part + ((int64_t)by * a.total_rows + it.row0) * ncols;
+  // the item's region spans all nb bins: tile row k n1 + b1 (k = 2 block +
+  // re/im) sits at k nb + o1 + b1, tile column (b2, b3) at (o2 + b2) nb + o3 + b3
+  const int64_t gcols = (int64_t)nb * nb;
+  double* part = a.part + ((int64_t)by * a.total_rows + it.row0) * gcols;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     if (!colok[t]) continue;
     const int j = 16 * (wr + W * t) + (lane & 15);
+    const int b2 = j / n3, b3 = j - b2 * n3;
+    const int64_t gj = (int64_t)(o2 + b2) * nb + o3 + b3;
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * m + 4 * r + (lane >> 4);
-        if (row < mrows) part[(int64_t)row * ncols + j] = acc[m][t][r];
+        if (row < mrows) {
+          const int k = (row >= n1) + (row >= 2 * n1) + (row >= 3 * n1);
+          part[(int64_t)(k * nb + o1 + row - k * n1) * gcols + gj] = acc[m][t][r];
+        }
       }
   }
 }
@@ -694,28 +733,31 @@ __global__ void pair_reduce_kernel(const double* part, int nsl, int64_t slice_el
                                    const PairOut* out, int nb, int nmax, double* ups) {
   const int nn = 2 * nmax + 1;
   const int64_t total = 2LL * FPCF4_NCORR * nb * nb * nb * nn * nn;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int p = (int)(i & 1);
-  int64_t r = i >> 1;
-  const int n3i = (int)(r % nn); r /= nn;
-  const int n2i = (int)(r % nn); r /= nn;
-  const int b3 = (int)(r % nb); r /= nb;
-  const int b2 = (int)(r % nb); r /= nb;
-  const int b1 = (int)(r % nb); r /= nb;
-  const int mu = (int)r;
-  const PairOut po = out[((int64_t)mu * nn + n2i) * nn + n3i];
-  const int row = items[po.item].row0 + po.blk * 2 * nb + p * nb + b1;
-  const int col = po.transposed ? b3 * nb + b2 : b2 * nb + b3;
-  const int64_t src = (int64_t)row * nb * nb + col;
-  double v = 0.0;
-  for (int k = 0; k < nsl; ++k) v += part[(int64_t)k * slice_elems + src];
-  ups[i] += v;
+  // grid-stride: at 65 bins and nmax 15 there are 4.8e9 values, more
+  // work-items than one dispatch dimension holds (2^32)
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(i & 1);
+    int64_t r = i >> 1;
+    const int n3i = (int)(r % nn); r /= nn;
+    const int n2i = (int)(r % nn); r /= nn;
+    const int b3 = (int)(r % nb); r /= nb;
+    const int b2 = (int)(r % nb); r /= nb;
+    const int b1 = (int)(r % nb); r /= nb;
+    const int mu = (int)r;
+    const PairOut po = out[((int64_t)mu * nn + n2i) * nn + n3i];
+    const int row = items[po.item].row0 + po.blk * 2 * nb + p * nb + b1;
+    const int col = po.transposed ? b3 * nb + b2 : b2 * nb + b3;
+    const int64_t src = (int64_t)row * nb * nb + col;
+    double v = 0.0;
+    for (int k = 0; k < nsl; ++k) v += part[(int64_t)k * slice_elems + src];
+    ups[i] += v;
+  }
 }
 
 template <int PREC, int NBLK, int NBC>
 static void launch_cls(const PairArgs& a, int nsl, hipStream_t s) {
-  const dim3 grid(a.nitems, nsl), block(64 * pair_waves(NBLK, NBC));
+  const dim3 grid(a.nitems, nsl, a.nt * a.nt * a.nt), block(64 * pair_waves(NBLK, NBC));
   hipLaunchKernelGGL((contract_pair_kernel<PREC, NBLK, NBC>), grid, block, 0, s, a);
 }
 
@@ -727,7 +769,7 @@ static void launch_prec_nbc(const PairArgs& a, int nblk, int nsl, hipStream_t s)
 
 template <int NBC>
 static void launch_f64_nbc(const PairArgs& a, int nblk, int nsl, hipStream_t s) {
-  const dim3 grid(a.nitems, nsl);
+  const dim3 grid(a.nitems, nsl, a.nt * a.nt * a.nt);
   if (nblk == 1)
     hipLaunchKernelGGL((contract_pair_f64_kernel<1, NBC>), grid, dim3(64 * pair_waves(1, NBC)), 0, s, a);
   else
@@ -735,7 +777,8 @@ static void launch_f64_nbc(const PairArgs& a, int nblk, int nsl, hipStream_t s) 
 }
 
 double pair_issued_flops(const PairPlanHost& pp, int nb, int64_t ncent, int precision) {
-  const int nbc = nb <= 8 ? 8 : nb <= 12 ? 12 : 16;
+  const BinTiles bt = bin_tiles(nb);
+  const int nbc = bt.tb <= 8 ? 8 : bt.tb <= 12 ? 12 : 16;
   double f = 0.0;
   for (int k = 1; k <= PAIR_MAX_BLK; ++k) {
     const int cols = 16 * pair_waves(k, nbc) * pair_nt(k, nbc);   // surplus tiles included
@@ -743,12 +786,13 @@ double pair_issued_flops(const PairPlanHost& pp, int nb, int64_t ncent, int prec
     f += (double)pp.cls_count[k] * 16.0 * pair_mt(k, nbc) * cols * 2.0 * 2.0 *
          (precision == FPCF4_FP64 ? 1.0 : 3.0);
   }
-  return f * (double)ncent;
+  return f * (double)ncent * bt.nt * bt.nt * bt.nt;
 }
 
 hipError_t launch_contract_pairs(const PairLaunch& pl, hipStream_t s) {
   if (pl.ncent <= 0) return hipSuccess;
-  const int nsl = pair_slices(pl.ncent);
+  const int nsl = std::min(pair_slices(pl.ncent), std::max(1, pl.max_slices));
+  const BinTiles bt = bin_tiles(pl.nb);
   for (int nblk = 1; nblk <= PAIR_MAX_BLK; ++nblk) {
     if (pl.cls_count[nblk] == 0) continue;
     PairArgs a{};
@@ -763,16 +807,19 @@ hipError_t launch_contract_pairs(const PairLaunch& pl, hipStream_t s) {
     a.ncent = pl.ncent;
     a.nb = pl.nb;
     a.nmax = pl.nmax;
+    a.tb = bt.tb;
+    a.nt = bt.nt;
     a.part = pl.part;
     a.total_rows = pl.total_rows;
+    // kernel class by the bins per tile
     if (pl.precision == FPCF4_FP64) {
-      if (pl.nb <= 8) launch_f64_nbc<8>(a, nblk, nsl, s);
-      else if (pl.nb <= 12) launch_f64_nbc<12>(a, nblk, nsl, s);
+      if (bt.tb <= 8) launch_f64_nbc<8>(a, nblk, nsl, s);
+      else if (bt.tb <= 12) launch_f64_nbc<12>(a, nblk, nsl, s);
       else launch_f64_nbc<16>(a, nblk, nsl, s);
-    } else if (pl.nb <= 8) {
+    } else if (bt.tb <= 8) {
       if (pl.precision == FPCF4_MIXED_FP16) launch_prec_nbc<FPCF4_MIXED_FP16, 8>(a, nblk, nsl, s);
       else launch_prec_nbc<FPCF4_MIXED_BF16, 8>(a, nblk, nsl, s);
-    } else if (pl.nb <= 12) {
+    } else if (bt.tb <= 12) {
       if (pl.precision == FPCF4_MIXED_FP16) launch_prec_nbc<FPCF4_MIXED_FP16, 12>(a, nblk, nsl, s);
       else launch_prec_nbc<FPCF4_MIXED_BF16, 12>(a, nblk, nsl, s);
     } else {
@@ -784,7 +831,8 @@ hipError_t launch_contract_pairs(const PairLaunch& pl, hipStream_t s) {
   }
   const int nn = 2 * pl.nmax + 1;
   const int64_t total = 2LL * FPCF4_NCORR * pl.nb * pl.nb * pl.nb * nn * nn;
-  hipLaunchKernelGGL(pair_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, pl.part, nsl,
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1 << 16);
+  hipLaunchKernelGGL(pair_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pl.part, nsl,
                      pl.total_rows * pl.nb * pl.nb, pl.items, pl.out, pl.nb, pl.nmax, pl.ups);
   return hipGetLastError();
 }

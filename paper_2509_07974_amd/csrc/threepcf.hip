@@ -84,7 +84,13 @@ __host__ __device__ inline int slice_len(int ncent, int parts) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void contract3_kernel(ThreeArgs a) {
-  const int ni = blockIdx.x;
+  // blockIdx.x = ni nt^2 + bin tile (t1, t2): b1 in [o1, o1 + n1), b2 in [o2, o2 + n2)
+  const BinTiles bt = bin_tiles(a.nb);
+  const int ntt = bt.nt * bt.nt;
+  const int ni = (int)blockIdx.x / ntt;
+  const int t12 = (int)blockIdx.x % ntt;
+  const int o1 = (t12 / bt.nt) * bt.tb, o2 = (t12 % bt.nt) * bt.tb;
+  const int n1 = min(bt.tb, a.nb - o1), n2 = min(bt.tb, a.nb - o2);
   const int mu = blockIdx.y;
   const int sl = blockIdx.z;
   const int n = ni - a.m;
@@ -95,22 +101,22 @@ __global__ __launch_bounds__(256) void contract3_kernel(ThreeArgs a) {
   const int per = slice_len(a.ncent, THREE_SLICES);
   const int c0 = sl * per;
   const int c1 = min(a.ncent, c0 + per);
-  __shared__ double2 Ls[FPCF4_NBINS_SUPPORTED][CH3 + 1];
-  __shared__ double2 Rs[FPCF4_NBINS_SUPPORTED][CH3 + 1];
+  __shared__ double2 Ls[BIN_TILE_MAX][CH3 + 1];
+  __shared__ double2 Rs[BIN_TILE_MAX][CH3 + 1];
   const int t = threadIdx.x;
-  const bool owner = t < nb * nb;
-  const int b1 = owner ? t / nb : 0, b2 = owner ? t % nb : 0;
+  const bool owner = t < n1 * n2;
+  const int b1 = owner ? t / n2 : 0, b2 = owner ? t % n2 : 0;
   const T* rec = static_cast<const T*>(a.rec);
   double ar = 0.0, ai = 0.0;
   for (int cb = c0; cb < c1; cb += CH3) {
-    for (int q = t; q < 2 * nb * CH3; q += blockDim.x) {
-      const int side = q / (nb * CH3);
-      const int rem = q - side * nb * CH3;
+    for (int q = t; q < (n1 + n2) * CH3; q += blockDim.x) {
+      const int side = q >= n1 * CH3;
+      const int rem = side ? q - n1 * CH3 : q;
       const int b = rem / CH3, c = rem - (rem / CH3) * CH3;
       const int ci = cb + c;
       double vr = 0.0, vi = 0.0;
       if (ci < c1) {
-        const size_t o = (((size_t)(side ? e2 : e1) * nb + b) * a.ldc + ci) * 2;
+        const size_t o = (((size_t)(side ? e2 : e1) * nb + (side ? o2 : o1) + b) * a.ldc + ci) * 2;
         vr = (double)rec[o];
         vi = (double)rec[o + 1];
         if (side ? r.f2.conj : r.f1.conj) vi = -vi;
@@ -139,20 +145,23 @@ __global__ __launch_bounds__(256) void contract3_kernel(ThreeArgs a) {
     __syncthreads();
   }
   if (owner) {
-    double* p = a.part + 2 * ((size_t)sl * three_elems(nb, a.m) + ((size_t)mu * a.nn + ni) * nb * nb + t);
+    double* p = a.part + 2 * ((size_t)sl * three_elems(nb, a.m) + ((size_t)mu * a.nn + ni) * nb * nb +
+                              (size_t)(o1 + b1) * nb + o2 + b2);
     p[0] = ar;
     p[1] = ai;
   }
 }
 
 // same-neighbour sums sum_i x_i D_mu(i, b) for every bin: one workgroup per
-// (mu, centre slice), centres strided over the threads, then a fixed-order
-// tree reduction over the workgroup.
+// (mu, centre slice, bin tile), centres strided over the threads, then a
+// fixed-order tree reduction over the workgroup.
 template <typename T>
 __global__ __launch_bounds__(256) void diag3_kernel(ThreeArgs a) {
   const int mu = blockIdx.x;
   const int sl = blockIdx.y;
   const int nb = a.nb;
+  const BinTiles bt = bin_tiles(nb);
+  const int ob = (int)blockIdx.z * bt.tb, nbt = min(bt.tb, nb - ob);
   const Layout L = make_layout(a.n4);
   const Row3 r = row3(mu);
   const int ed = r.dfam == 0 ? eQ(L, r.dord) : r.dfam == 1 ? eA(L, r.dord) : eV(L, r.dord);
@@ -160,16 +169,16 @@ __global__ __launch_bounds__(256) void diag3_kernel(ThreeArgs a) {
   const int c0 = sl * per;
   const int c1 = min(a.ncent, c0 + per);
   const T* rec = static_cast<const T*>(a.rec);
-  double accr[FPCF4_NBINS_SUPPORTED], acci[FPCF4_NBINS_SUPPORTED];
+  double accr[BIN_TILE_MAX], acci[BIN_TILE_MAX];
 #pragma unroll
-  for (int b = 0; b < FPCF4_NBINS_SUPPORTED; ++b) accr[b] = acci[b] = 0.0;
+  for (int b = 0; b < BIN_TILE_MAX; ++b) accr[b] = acci[b] = 0.0;
   for (int ci = c0 + (int)threadIdx.x; ci < c1; ci += blockDim.x) {
     double xr, xi;
     centre_factor<T>(a, r.x, ci, xr, xi);
 #pragma unroll
-    for (int b = 0; b < FPCF4_NBINS_SUPPORTED; ++b) {
-      if (b < nb) {
-        const size_t o = (((size_t)ed * nb + b) * a.ldc + ci) * 2;
+    for (int b = 0; b < BIN_TILE_MAX; ++b) {
+      if (b < nbt) {
+        const size_t o = (((size_t)ed * nb + ob + b) * a.ldc + ci) * 2;
         const double vr = (double)rec[o];
         const double vi = r.dconj ? -(double)rec[o + 1] : (double)rec[o + 1];
         accr[b] = fma(xr, vr, fma(-xi, vi, accr[b]));
@@ -182,8 +191,8 @@ __global__ __launch_bounds__(256) void diag3_kernel(ThreeArgs a) {
   double* out = a.part + 2 * ((size_t)sl * three_elems(nb, a.m) + (size_t)5 * a.nn * nb * nb +
                               (size_t)mu * nb);
 #pragma unroll
-  for (int b = 0; b < FPCF4_NBINS_SUPPORTED; ++b) {
-    if (b < nb) {
+  for (int b = 0; b < BIN_TILE_MAX; ++b) {
+    if (b < nbt) {
       red[t] = make_double2(accr[b], acci[b]);
       __syncthreads();
       for (int s = 128; s > 0; s >>= 1) {
@@ -194,8 +203,8 @@ __global__ __launch_bounds__(256) void diag3_kernel(ThreeArgs a) {
         __syncthreads();
       }
       if (t == 0) {
-        out[2 * b] = red[0].x;
-        out[2 * b + 1] = red[0].y;
+        out[2 * (ob + b)] = red[0].x;
+        out[2 * (ob + b) + 1] = red[0].y;
       }
       __syncthreads();
     }
@@ -240,10 +249,11 @@ template <typename T>
 hipError_t launch_three(const ThreeArgs& a, hipStream_t s) {
   if (a.ncent <= 0) return hipSuccess;
   if (a.nb < 1 || a.nb > FPCF4_NBINS_SUPPORTED || a.m < 0 || a.m > 2 * a.n4) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(contract3_kernel<T>, dim3(a.nn, 5, THREE_SLICES), dim3(256), 0, s, a);
+  const BinTiles bt = bin_tiles(a.nb);
+  hipLaunchKernelGGL(contract3_kernel<T>, dim3(a.nn * bt.nt * bt.nt, 5, THREE_SLICES), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(diag3_kernel<T>, dim3(5, THREE_SLICES), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(diag3_kernel<T>, dim3(5, THREE_SLICES, bt.nt), dim3(256), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t elems2 = 2 * three_elems(a.nb, a.m);

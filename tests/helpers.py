@@ -79,16 +79,20 @@ def _scale_for(bound, ncorr, shape_tail):
                      for m in range(ncorr)])
 
 
-def parity_metrics(a, b, bound=None, nbin=3):
+def parity_metrics(a, b, bound=None, nbin=3, eq=None):
     """Per correlator: normwise, max-element, element-wise (entries >= 1e-3
     max) and, given the oracle's term scale `bound`, scaled element errors, of
     a against the reference b ([ncorr, nb x nbin, multipoles...]); each also
-    over the equal-bin tuples alone (prefix eq_)."""
+    over the equal-bin tuples alone (prefix eq_).  For a list of bin tuples
+    instead ([ncorr, ntuple, multipoles...], `bound` [2, ntuple]) pass `eq`,
+    the mask of the tuples with equal bins."""
     a = np.asarray(a)
     b = np.asarray(b)
     nb = b.shape[1]
-    eq = equal_bin_mask(nb, nbin)
-    tail = b.shape[1 + nbin:]
+    if eq is None:
+        eq = equal_bin_mask(nb, nbin)
+    eq = np.asarray(eq, dtype=bool)
+    tail = b.shape[1 + eq.ndim:]
     S = _scale_for(bound, b.shape[0], tail)
     ae, be = a[:, eq], b[:, eq]
     out = {"norm": rel_per_mu(a, b), "max": maxabs_per_mu(a, b), "elem": elem_per_mu(a, b),
@@ -100,11 +104,11 @@ def parity_metrics(a, b, bound=None, nbin=3):
     return out
 
 
-def assert_parity(a, b, prec, bound=None, nbin=3, label="", bars=None):
+def assert_parity(a, b, prec, bound=None, nbin=3, label="", bars=None, eq=None):
     """Every metric of parity_metrics within the bars of `prec` (the
     equal-bin tuples within the same bars as the whole tensor)."""
     bars = dict(BARS[prec], **(bars or {}))
-    m = parity_metrics(a, b, bound, nbin)
+    m = parity_metrics(a, b, bound, nbin, eq)
     print(label, prec, {k: float(v.max()) for k, v in m.items()}, flush=True)
     for key, tol in bars.items():
         for k in (key, "eq_" + key):

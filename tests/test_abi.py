@@ -51,7 +51,7 @@ def _call(edges, nmax=2, n=10, precision=0, xs=None):
     ([1.0, np.nan, 3.0], 2, -1),       # non-finite edge
     ([1.0, 2.0], -1, -1),              # nmax < 0
     ([1.0, 2.0], 17, -2),              # beyond compiled nmax
-    (list(np.geomspace(1, 10, 18)), 2, -2),   # 17 bins > 16
+    (list(np.geomspace(1, 10, 130)), 2, -2),  # 129 bins > 128
     ([1.0], 2, -1),                    # no bin
 ])
 def test_invalid_arguments_rejected(edges, nmax, code):
@@ -96,7 +96,7 @@ def _call3(edges, nmax=2, n=10, precision=0):
     ([0.0, 1.0, 2.0], 4, -1),          # edges[0] <= 0
     ([1.0, 2.0], -1, -1),              # nmax < 0
     ([1.0, 2.0], 33, -2),              # beyond the compiled 3PCF multipoles
-    (list(np.geomspace(1, 10, 18)), 2, -2),   # 17 bins > 16
+    (list(np.geomspace(1, 10, 130)), 2, -2),  # 129 bins > 128
 ])
 def test_3pcf_invalid_arguments_rejected(edges, nmax, code):
     st, msg = _call3(edges, nmax)
