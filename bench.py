@@ -338,6 +338,18 @@ def natural_report(fp, ups_dev, nphi, block=256):
 THREEPCF_NMAX = 10   # 3PCF multipoles |n| <= 10 (stage (a) records of order 5)
 
 
+BASETREE = (0.5, 3, 40.0)    # base grids 0.5', 1', 2'; a bin uses the coarsest with edge / grid >= 40
+
+
+def grid_levels(edges, delta1, nlevels, rmin):
+    """Grid of each radial bin: the coarsest d with edges[b] / (delta1 2^(d-1)) >= rmin, 0 if none."""
+    out = []
+    for e in edges[:-1]:
+        ok = [d for d in range(1, nlevels + 1) if e / (delta1 * 2.0 ** (d - 1)) >= rmin]
+        out.append(max(ok) if ok else 0)
+    return out
+
+
 def threepcf_report(fp, dev, n, edges, precision, no_fp64):
     """The shear 3PCF on the same catalogue: one warmup and two timed
     estimates (per-stage times from the library's events), and the FP64 path
@@ -362,6 +374,27 @@ def threepcf_report(fp, dev, n, edges, precision, no_fp64):
            "stage_ms_per_step": {"stage_a": prof["stage_a_ms"] / 2, "relayout": prof["relayout_ms"] / 2,
                                  "contraction_and_same_neighbour": prof["stage_b_ms"] / 2}}
     log(f"3pcf: {dt:.3f} s/step")
+    if precision != "fp64":
+        # BaseTree: base points on grids of 0.5', 1', 2' (r_min 40, the tree
+        # setting of the paper's survey measurement)
+        def run_bt():
+            return fp.estimate_3pcf_multipoles(*dev, edges, THREEPCF_NMAX, precision=precision, base=BASETREE)
+        run_bt()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(2):
+            bto = run_bt()
+        torch.cuda.synchronize()
+        dbt = (time.perf_counter() - t) / 2
+        a, b = bto.cpu().numpy(), out.cpu().numpy()
+        rep["basetree"] = {
+            "delta1": BASETREE[0], "levels": BASETREE[1], "rmin": BASETREE[2],
+            "bin_grids": grid_levels(edges, *BASETREE),
+            "ms_per_step": dbt * 1e3, "value": n / dbt, "unit": "centres/s",
+            "speedup_vs_discrete": dt / dbt,
+            "deviation_from_discrete_per_mu": [float(np.linalg.norm(a[m] - b[m]) / np.linalg.norm(b[m]))
+                                               for m in range(5)]}
+        log(f"3pcf basetree: {dbt:.3f} s/step ({dt / dbt:.2f}x)")
     if not no_fp64 and precision != "fp64":
         run("fp64")
         torch.cuda.synchronize()

@@ -440,6 +440,7 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
   a.cat.cell_start = R->at<int32_t>(P.o_cells);
   a.cat.g = R->grid;
   a.centres = R->at<int32_t>(P.o_centres) + c0;
+  a.cgal = a.cat.gal;
   a.ncent = ncent;
   a.nb = P.nb;
   a.ldc = (int32_t)P.ldc;
@@ -466,7 +467,8 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
   if (prof) HIPCHK(hipEventRecord(evs[2], s));
   if (stage_b && P.order == 3) {
     ThreeArgs t3{a.rec, a.xg, a.xw, ncent, P.nb, P.nmax, P.m3, 2 * P.m3 + 1, (int32_t)P.ldc,
-                 R->at<double>(P.o_part3), R->at<double>(P.o_acc3)};
+                 R->at<double>(P.o_part3), R->at<double>(P.o_acc3),
+                 a.rec, (int32_t)P.ldc, nullptr, nullptr, 0, P.nb, 0, P.nb};
     if (P.precision == FPCF4_FP64) HIPCHK(launch_three<double>(t3, s));
     else HIPCHK(launch_three<float>(t3, s));
     if (prof) {
@@ -514,6 +516,229 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
     }
   }
   R->stepped[(size_t)tile] = 1;
+  return FPCF4_OK;
+}
+
+// ---------------------------------------------------------------------------
+// BaseTree / DoubleTree shear 3PCF (the appendix on Nth-order statistics,
+// algorithmic implementation): base points on reduced catalogues, one grid
+// per radial bin; x times the finer-bin block is carried to the coarser
+// grid through the parent map of nested cells.
+// ---------------------------------------------------------------------------
+__global__ void base_centres_kernel(const GalR<float>* r, int64_t m, Gal<float>* g, int32_t* idx) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const GalR<float> q = r[i];
+    g[i] = Gal<float>{q.x, q.y, q.a, q.b, q.w, 0.0f};
+    idx[i] = (int32_t)i;
+  }
+}
+// parent of every discrete base point (record column c, sorted position
+// centres[c]) on a coarser grid
+__global__ void parent_galaxy_kernel(const int32_t* centres, const int32_t* sorted_to_orig,
+                                     const int32_t* member, int64_t n, int32_t* par) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x)
+    par[c] = member[sorted_to_orig[centres[c]]];
+}
+// parent of every pseudo-galaxy of a finer grid: each of its galaxies names
+// the same coarse cell (nested grids), so the writes agree
+__global__ void parent_cell_kernel(const int32_t* member_f, const int32_t* member_c, int64_t n,
+                                   int32_t* par) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x)
+    par[member_f[g]] = member_c[g];
+}
+__global__ void zero_f64_kernel(double* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+int blocks_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1 << 16)); }
+
+fpcf4_status check_tree(const fpcf4_tree* t, const char* what) {
+  if (t->nlevels < 1 || t->nlevels > TREE_LEVELS_MAX)
+    return fail(FPCF4_E_INVALID_ARG, "%s levels %d not in 1..%d", what, t->nlevels, TREE_LEVELS_MAX);
+  if (!(t->delta1 > 0.0) || !std::isfinite(t->delta1)) return fail(FPCF4_E_INVALID_ARG, "%s delta1 must be > 0", what);
+  if (!(t->rmin >= 2.0) || !std::isfinite(t->rmin)) return fail(FPCF4_E_INVALID_ARG, "%s rmin must be >= 2", what);
+  return FPCF4_OK;
+}
+
+// Device buffers of the driver, freed in reverse order on the stream.
+struct StreamBuffers {
+  hipStream_t s;
+  std::vector<void*> p;
+  explicit StreamBuffers(hipStream_t st) : s(st) {}
+  hipError_t get(void** out, size_t bytes) {
+    *out = nullptr;
+    hipError_t e = hipMallocAsync(out, std::max<size_t>(bytes, 256), s);
+    if (e == hipSuccess) p.push_back(*out);
+    return e;
+  }
+  ~StreamBuffers() {
+    for (auto it = p.rbegin(); it != p.rend(); ++it) (void)hipFreeAsync(*it, s);
+  }
+};
+
+fpcf4_status run_3pcf_basetree(fpcf4_request* R, const fpcf4_catalogue* cat, const fpcf4_bins* bins,
+                               const fpcf4_tree* base) {
+  PlanInfo& P = R->P;
+  hipStream_t s = R->stream;
+  const int64_t n = P.n;
+  const int nb = P.nb;
+  // base grid of every bin (coarsest d with edges[b] / Delta_d >= rmin), a
+  // non-decreasing function of b: the bins of one grid are a range
+  int lvl[FPCF4_NBINS_SUPPORTED];
+  for (int b = 0; b < nb; ++b) {
+    int best = 0;
+    for (int d = 1; d <= base->nlevels; ++d)
+      if (bins->edges[b] / (base->delta1 * std::ldexp(1.0, d - 1)) >= base->rmin) best = d;
+    lvl[b] = best;
+  }
+  int lo[TREE_LEVELS_MAX + 1], hi[TREE_LEVELS_MAX + 1];
+  for (int d = 0; d <= TREE_LEVELS_MAX; ++d) lo[d] = hi[d] = -1;
+  for (int b = 0; b < nb; ++b) {
+    if (lo[lvl[b]] < 0) lo[lvl[b]] = b;
+    hi[lvl[b]] = b + 1;
+  }
+  std::vector<int> D;
+  for (int d = 0; d <= TREE_LEVELS_MAX; ++d)
+    if (lo[d] >= 0) D.push_back(d);
+
+  StreamBuffers buf(s);
+  const Layout L = make_layout(P.nmax);
+  const size_t rec_per_centre = (size_t)nb * L.mpc * 2 * sizeof(float);
+  // per grid: base points, records, centre factors; member maps of the galaxies
+  struct Grid_ {
+    int64_t m = 0, ldc = 0;
+    const void* cgal = nullptr;
+    const int32_t* centres = nullptr;
+    void* rec = nullptr;
+    void* xg = nullptr;
+    void* xw = nullptr;
+    int32_t* member = nullptr;
+  } G[TREE_LEVELS_MAX + 1];
+  // the discrete grid: the request's own sorted catalogue and buffers
+  G[0].m = P.ncent;
+  G[0].ldc = P.ldc;
+  G[0].cgal = R->ws + P.o_gal;
+  G[0].centres = R->at<int32_t>(P.o_centres);
+  G[0].rec = R->ws + P.o_region;
+  G[0].xg = R->ws + P.o_xg;
+  G[0].xw = R->ws + P.o_xw;
+  // raw catalogue (a host catalogue's device copy sits in the region, which
+  // the discrete grid's records overwrite only after the reduced builds)
+  const double *x, *y, *g1, *g2, *w;
+  if (cat->mem == FPCF4_MEM_HOST) {
+    const double* raw = reinterpret_cast<const double*>(R->ws + P.o_region + P.t_raw);
+    x = raw; y = raw + n; g1 = raw + 2 * n; g2 = raw + 3 * n; w = raw + 4 * n;
+  } else {
+    x = cat->x; y = cat->y; g1 = cat->g1; g2 = cat->g2; w = cat->w;
+  }
+  double bb[4];
+  HIPCHK(hipMemcpyAsync(bb, R->ws + P.o_bbox, 32, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  void* scratch = nullptr;
+  const bool any_red = D.back() > 0;
+  if (any_red) HIPCHK(buf.get(&scratch, reduced_scratch_bytes(n)));
+  for (int d : D) {
+    if (d == 0) continue;
+    void *galr, *cs, *mem, *cg, *ci;
+    HIPCHK(buf.get(&galr, (size_t)n * sizeof(GalR<float>)));
+    HIPCHK(buf.get(&cs, ((size_t)R->grid.ncx * R->grid.ncy + 1) * 4));
+    HIPCHK(buf.get(&mem, (size_t)n * 4));
+    int64_t m = 0;
+    HIPCHK(reduced_build(x, y, g1, g2, w, n, bb[0], bb[2], bb[1], bb[3], base->delta1 * std::ldexp(1.0, d - 1),
+                         R->grid, scratch, galr, reinterpret_cast<int32_t*>(cs), &m, s,
+                         reinterpret_cast<int32_t*>(mem)));
+    HIPCHK(buf.get(&cg, (size_t)std::max<int64_t>(m, 1) * sizeof(Gal<float>)));
+    HIPCHK(buf.get(&ci, (size_t)std::max<int64_t>(m, 1) * 4));
+    hipLaunchKernelGGL(base_centres_kernel, dim3(blocks_for(m)), dim3(256), 0, s,
+                       reinterpret_cast<const GalR<float>*>(galr), m, reinterpret_cast<Gal<float>*>(cg),
+                       reinterpret_cast<int32_t*>(ci));
+    HIPCHK(hipGetLastError());
+    G[d].m = m;
+    G[d].ldc = (m + 15) / 16 * 16;
+    G[d].cgal = cg;
+    G[d].centres = reinterpret_cast<const int32_t*>(ci);
+    G[d].member = reinterpret_cast<int32_t*>(mem);
+    HIPCHK(buf.get(&G[d].rec, (size_t)G[d].ldc * rec_per_centre));
+    HIPCHK(buf.get(&G[d].xg, (size_t)G[d].ldc * 2 * sizeof(float)));
+    HIPCHK(buf.get(&G[d].xw, (size_t)G[d].ldc * sizeof(float)));
+  }
+  // parent maps from every grid to every coarser one (before the discrete
+  // records overwrite the sort's index arrays in the region)
+  int32_t* par[TREE_LEVELS_MAX + 1][TREE_LEVELS_MAX + 1] = {};
+  const int32_t* sorted_to_orig = reinterpret_cast<const int32_t*>(R->ws + P.o_region + P.t_idx_b);
+  for (int f : D)
+    for (int c : D) {
+      if (c <= f) continue;
+      void* pp;
+      HIPCHK(buf.get(&pp, (size_t)std::max<int64_t>(G[f].m, 1) * 4));
+      par[f][c] = reinterpret_cast<int32_t*>(pp);
+      if (f == 0)
+        hipLaunchKernelGGL(parent_galaxy_kernel, dim3(blocks_for(G[0].m)), dim3(256), 0, s, G[0].centres,
+                           sorted_to_orig, G[c].member, G[0].m, par[f][c]);
+      else
+        hipLaunchKernelGGL(parent_cell_kernel, dim3(blocks_for(n)), dim3(256), 0, s, G[f].member,
+                           G[c].member, n, par[f][c]);
+      HIPCHK(hipGetLastError());
+    }
+  // stage (a): the blocks of every bin at the base points of its grid
+  int32_t* counters = R->at<int32_t>(P.o_counters);
+  for (int d : D) {
+    hipLaunchKernelGGL(zero_kernel, dim3((kCounterWords + 255) / 256), dim3(256), 0, s, counters, kCounterWords);
+    HIPCHK(hipGetLastError());
+    StageAArgs a{};
+    a.cat.n = P.n;
+    a.cat.gal = R->ws + P.o_gal;
+    a.cat.cell_start = R->at<int32_t>(P.o_cells);
+    a.cat.g = R->grid;
+    a.centres = G[d].centres;
+    a.cgal = G[d].cgal;
+    a.ncent = (int32_t)G[d].m;
+    a.nb = nb;
+    a.ldc = (int32_t)G[d].ldc;
+    a.xg = G[d].xg;
+    a.xw = G[d].xw;
+    a.maxima = nullptr;
+    a.e2 = R->at<double>(P.o_e2);
+    a.edges = R->at<double>(P.o_edges);
+    a.rec = G[d].rec;
+    a.rec_aos = R->ws + P.o_aos;
+    a.counts = nullptr;
+    a.work_counter = counters;
+    a.pairs = R->at<unsigned long long>(P.o_pairs);
+    a.b_lo = lo[d];
+    a.b_hi = hi[d];
+    for (int b = 0; b < nb; ++b) a.level[b] = P.level[b];
+    for (int t = 1; t <= P.tree_levels; ++t) {
+      a.rgal[t - 1] = R->ws + P.o_rgal[t - 1];
+      a.rcell[t - 1] = R->at<int32_t>(P.o_rcell[t - 1]);
+    }
+    int nl = 0;
+    if (G[d].m > 0) HIPCHK(launch_stage_a<float>(P.nmax, 3, a, s, &nl, nullptr));
+  }
+  // contraction for every pair of grids: over the base points of the finer
+  // one, the coarser slot read at the parent; each pair writes only its own
+  // bins of the zeroed slice partials, which are then added to the sums
+  double* part = R->at<double>(P.o_part3);
+  const int64_t part_elems = (int64_t)THREE_SLICES * 2 * (int64_t)three_elems(nb, P.m3);
+  for (int d1 : D)
+    for (int d2 : D) {
+      const int f = std::min(d1, d2);
+      if (G[f].m == 0) continue;
+      hipLaunchKernelGGL(zero_f64_kernel, dim3(blocks_for(part_elems)), dim3(256), 0, s, part, part_elems);
+      HIPCHK(hipGetLastError());
+      ThreeArgs t{G[d1].rec, G[f].xg, G[f].xw, (int32_t)G[f].m, nb, P.nmax, P.m3, 2 * P.m3 + 1,
+                  (int32_t)G[d1].ldc, part, R->at<double>(P.o_acc3),
+                  G[d2].rec, (int32_t)G[d2].ldc, d1 > f ? par[f][d1] : nullptr, d2 > f ? par[f][d2] : nullptr,
+                  lo[d1], hi[d1] - lo[d1], lo[d2], hi[d2] - lo[d2]};
+      HIPCHK(launch_three<float>(t, s));
+    }
+  HIPCHK(hipStreamSynchronize(s));
+  R->stepped.assign(R->stepped.size(), 1);
   return FPCF4_OK;
 }
 
@@ -737,6 +962,44 @@ fpcf4_status estimate_3pcf_multipoles(const fpcf4_catalogue* cat, const fpcf4_bi
   if (!R) st = fail(FPCF4_E_OUT_OF_MEMORY, "host allocation failed");
   if (st == FPCF4_OK) st = request_init(cat, bins, &o, ws, P.total, R, 3, m);
   for (int64_t t = 0; st == FPCF4_OK && t < P.ntiles; ++t) st = request_step(R, t, true);
+  if (st == FPCF4_OK) st = fpcf4_request_finalize(R, upsilon3, out_mem);
+  delete R;
+  hipError_t e = hipFreeAsync(ws, s);
+  if (st == FPCF4_OK && e != hipSuccess) return fail(FPCF4_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));
+  return st;
+}
+
+fpcf4_status estimate_3pcf_multipoles_basetree(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
+                                               const fpcf4_options* opts, const fpcf4_tree* base,
+                                               double* upsilon3, int32_t out_mem) {
+  if (!upsilon3 || !opts || !base) return fail(FPCF4_E_INVALID_ARG, "null argument");
+  if (out_mem != FPCF4_MEM_HOST && out_mem != FPCF4_MEM_DEVICE) return fail(FPCF4_E_INVALID_ARG, "out_mem %d", out_mem);
+  if (opts->nmax < 0) return fail(FPCF4_E_INVALID_ARG, "nmax < 0");
+  if (opts->nmax > FPCF4_NMAX3_SUPPORTED)
+    return fail(FPCF4_E_UNSUPPORTED, "3PCF nmax %d > %d", opts->nmax, FPCF4_NMAX3_SUPPORTED);
+  fpcf4_status st = check_tree(base, "base");
+  if (st != FPCF4_OK) return st;
+  if (opts->precision == FPCF4_FP64)
+    return fail(FPCF4_E_UNSUPPORTED, "the BaseTree approximation runs in the mixed paths only");
+  if (opts->centers) return fail(FPCF4_E_INVALID_ARG, "BaseTree: every galaxy is a base point (no centre subset)");
+  const int m = opts->nmax;
+  fpcf4_options o = *opts;
+  o.nmax = (m + 1) / 2;
+  o.tile_centers = 0;
+  PlanInfo P;
+  st = make_plan(cat, bins, &o, P, 3, m);
+  if (st != FPCF4_OK) return st;
+  if (P.ntiles > 1)
+    return fail(FPCF4_E_UNSUPPORTED, "BaseTree: the records of all %lld galaxies must fit one tile",
+                (long long)P.n);
+  setup_pool();
+  hipStream_t s = static_cast<hipStream_t>(o.stream);
+  void* ws = nullptr;
+  HIPCHK(hipMallocAsync(&ws, P.total, s));
+  fpcf4_request* R = new (std::nothrow) fpcf4_request();
+  if (!R) st = fail(FPCF4_E_OUT_OF_MEMORY, "host allocation failed");
+  if (st == FPCF4_OK) st = request_init(cat, bins, &o, ws, P.total, R, 3, m);
+  if (st == FPCF4_OK && P.n > 0) st = run_3pcf_basetree(R, cat, bins, base);
   if (st == FPCF4_OK) st = fpcf4_request_finalize(R, upsilon3, out_mem);
   delete R;
   hipError_t e = hipFreeAsync(ws, s);

@@ -308,6 +308,20 @@ __global__ void rgather_kernel(const double* pd, int64_t ldp, const int32_t* per
   }
 }
 
+// pseudo-galaxy of every galaxy: seg_final[segment] = final index, then
+// out[original index] = seg_final[segment of its sorted position]
+__global__ void rinvert_kernel(const int32_t* pb, int64_t m, int32_t* seg_final) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x)
+    seg_final[pb[i]] = (int32_t)i;
+}
+__global__ void rmember_kernel(const int32_t* ib, const int32_t* head, const int32_t* segid,
+                               const int32_t* seg_final, int64_t n, int32_t* out) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    out[ib[t]] = seg_final[segid[t] + head[t] - 1];
+}
+
 namespace {
 struct RedLayout {
   size_t k64a, k64b, ia, ib, head, segid, segstart, pd, ka, kb, pa, pb, tmp, tmp_bytes, total;
@@ -348,7 +362,7 @@ size_t reduced_scratch_bytes(int64_t n) { return red_layout(n).total; }
 hipError_t reduced_build(const double* x, const double* y, const double* g1, const double* g2,
                          const double* w, int64_t n, double x0, double y0, double xmax, double ymax,
                          double delta, const Grid& g, void* scratch, void* gal_out,
-                         int32_t* cell_start, int64_t* m_out, hipStream_t s) {
+                         int32_t* cell_start, int64_t* m_out, hipStream_t s, int32_t* member) {
   *m_out = 0;
   if (n <= 0) return hipSuccess;
   const RedLayout L = red_layout(n);
@@ -398,6 +412,11 @@ hipError_t reduced_build(const double* x, const double* y, const double* g1, con
   hipLaunchKernelGGL(starts_kernel, dim3(grid1d(m + 1)), dim3(256), 0, s, kb, m, ncells, cell_start);
   hipLaunchKernelGGL(rgather_kernel, dim3(grid1d(m)), dim3(256), 0, s, pd, n, pb, m,
                      reinterpret_cast<GalR<float>*>(gal_out));
+  if (member != nullptr) {
+    // pa is free once the sort has consumed it
+    hipLaunchKernelGGL(rinvert_kernel, dim3(grid1d(m)), dim3(256), 0, s, pb, m, pa);
+    hipLaunchKernelGGL(rmember_kernel, dim3(grid1d(n)), dim3(256), 0, s, ib, head, segid, pa, n, member);
+  }
   *m_out = m;
   return hipGetLastError();
 }

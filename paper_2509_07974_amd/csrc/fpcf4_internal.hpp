@@ -126,7 +126,8 @@ struct SortedCat {
 
 struct StageAArgs {
   SortedCat cat;
-  const int32_t* centres;   // sorted positions of this tile's centres
+  const int32_t* centres;   // positions in cgal of this tile's centres
+  const void* cgal;         // Gal<T> records of the centres: cat.gal, or base pseudo-galaxies
   int32_t ncent;
   int32_t nb;
   int32_t ldc;              // centre stride of record rows (>= ncent, multiple of 16)
@@ -152,11 +153,12 @@ struct StageAArgs {
 // approximation): pseudo-galaxies sorted on the search grid g, with cell
 // starts.  Scratch is caller-provided (reduced_scratch_bytes); returns the
 // number of pseudo-galaxies in *m (host, after a stream synchronisation).
+// member (optional, [n]): the pseudo-galaxy of every galaxy (catalogue order).
 size_t reduced_scratch_bytes(int64_t n);
 hipError_t reduced_build(const double* x, const double* y, const double* g1, const double* g2,
                          const double* w, int64_t n, double x0, double y0, double xmax, double ymax,
                          double delta, const Grid& g, void* scratch, void* gal_out,
-                         int32_t* cell_start, int64_t* m, hipStream_t s);
+                         int32_t* cell_start, int64_t* m, hipStream_t s, int32_t* member = nullptr);
 
 // stage (a) launcher, T = double or float: the pair-multipole kernel, then
 // the relayout of its records to centre-contiguous rows.  Returns the number
@@ -248,12 +250,20 @@ __host__ __device__ inline size_t three_elems(int nb, int m) {
   return (size_t)5 * (2 * m + 1) * nb * nb + (size_t)5 * nb;
 }
 struct ThreeArgs {
-  const void* rec;          // records of the tile (stage (a) of order n4)
+  const void* rec;          // records of the tile (stage (a) of order n4): the Theta_1 slot
   const void* xg;           // [ldc] complex (T): w g of each tile centre
   const void* xw;           // [ldc] (T): w of each tile centre
   int32_t ncent, nb, n4, m, nn, ldc;   // m: largest 3PCF multipole (<= 2 n4), nn = 2m+1
   double* part;             // [THREE_SLICES][three_elems] complex partial sums
   double* acc;              // [three_elems] complex, accumulated over tiles
+  // BaseTree: the Theta_2 slot may read other records (another base grid),
+  // and either slot may read its record at the centre's parent on a coarser
+  // grid.  Plain estimate: rec2 = rec, ldc2 = ldc, no parents, all bins.
+  const void* rec2;
+  int32_t ldc2;
+  const int32_t* par1;      // [ncent] record column of slot 1, or null (= centre)
+  const int32_t* par2;      // [ncent] record column of slot 2, or null
+  int32_t lo1, nb1, lo2, nb2;   // bins of slot 1: [lo1, lo1 + nb1); of slot 2 likewise
 };
 template <typename T> hipError_t launch_three(const ThreeArgs& a, hipStream_t s);
 // out[mu][b1][b2][n] (complex128) from the accumulator, minus the

@@ -545,7 +545,8 @@ __device__ __forceinline__ void pass_body(const StageAArgs& a,
   constexpr int FOLD = Budget<T>::fold;
   static_assert(NM <= Conf<T, N>::NMX, "staging block");
 
-  const Gal<T>* __restrict__ gal = reinterpret_cast<const Gal<T>*>(a.cat.gal);
+  // centres: the galaxies, or the pseudo-galaxies of a base grid (BaseTree)
+  const Gal<T>* __restrict__ gal = reinterpret_cast<const Gal<T>*>(a.cgal);
   const Grid g = a.cat.g;
   constexpr int NO = nord(N);   // record order
   const Layout L = make_layout(NO);

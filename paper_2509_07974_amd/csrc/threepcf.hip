@@ -84,13 +84,14 @@ __host__ __device__ inline int slice_len(int ncent, int parts) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void contract3_kernel(ThreeArgs a) {
-  // blockIdx.x = ni nt^2 + bin tile (t1, t2): b1 in [o1, o1 + n1), b2 in [o2, o2 + n2)
-  const BinTiles bt = bin_tiles(a.nb);
-  const int ntt = bt.nt * bt.nt;
+  // blockIdx.x = ni nt1 nt2 + bin tile (t1, t2): b1 in [o1, o1 + n1), b2 in
+  // [o2, o2 + n2), inside the slot ranges [lo1, lo1 + nb1) and [lo2, lo2 + nb2)
+  const BinTiles bt1 = bin_tiles(a.nb1), bt2 = bin_tiles(a.nb2);
+  const int ntt = bt1.nt * bt2.nt;
   const int ni = (int)blockIdx.x / ntt;
   const int t12 = (int)blockIdx.x % ntt;
-  const int o1 = (t12 / bt.nt) * bt.tb, o2 = (t12 % bt.nt) * bt.tb;
-  const int n1 = min(bt.tb, a.nb - o1), n2 = min(bt.tb, a.nb - o2);
+  const int o1 = a.lo1 + (t12 / bt2.nt) * bt1.tb, o2 = a.lo2 + (t12 % bt2.nt) * bt2.tb;
+  const int n1 = min(bt1.tb, a.lo1 + a.nb1 - o1), n2 = min(bt2.tb, a.lo2 + a.nb2 - o2);
   const int mu = blockIdx.y;
   const int sl = blockIdx.z;
   const int n = ni - a.m;
@@ -116,9 +117,12 @@ __global__ __launch_bounds__(256) void contract3_kernel(ThreeArgs a) {
       const int ci = cb + c;
       double vr = 0.0, vi = 0.0;
       if (ci < c1) {
-        const size_t o = (((size_t)(side ? e2 : e1) * nb + (side ? o2 : o1) + b) * a.ldc + ci) * 2;
-        vr = (double)rec[o];
-        vi = (double)rec[o + 1];
+        const int32_t* par = side ? a.par2 : a.par1;
+        const int col = par ? par[ci] : ci;
+        const T* rs = side ? static_cast<const T*>(a.rec2) : rec;
+        const size_t o = (((size_t)(side ? e2 : e1) * nb + (side ? o2 : o1) + b) * (side ? a.ldc2 : a.ldc) + col) * 2;
+        vr = (double)rs[o];
+        vi = (double)rs[o + 1];
         if (side ? r.f2.conj : r.f1.conj) vi = -vi;
         if (!side) {
           double xr, xi;
@@ -160,8 +164,8 @@ __global__ __launch_bounds__(256) void diag3_kernel(ThreeArgs a) {
   const int mu = blockIdx.x;
   const int sl = blockIdx.y;
   const int nb = a.nb;
-  const BinTiles bt = bin_tiles(nb);
-  const int ob = (int)blockIdx.z * bt.tb, nbt = min(bt.tb, nb - ob);
+  const BinTiles bt = bin_tiles(a.nb1);   // bins [lo1, lo1 + nb1) of the slot-1 records
+  const int ob = a.lo1 + (int)blockIdx.z * bt.tb, nbt = min(bt.tb, a.lo1 + a.nb1 - ob);
   const Layout L = make_layout(a.n4);
   const Row3 r = row3(mu);
   const int ed = r.dfam == 0 ? eQ(L, r.dord) : r.dfam == 1 ? eA(L, r.dord) : eV(L, r.dord);
@@ -249,11 +253,15 @@ template <typename T>
 hipError_t launch_three(const ThreeArgs& a, hipStream_t s) {
   if (a.ncent <= 0) return hipSuccess;
   if (a.nb < 1 || a.nb > FPCF4_NBINS_SUPPORTED || a.m < 0 || a.m > 2 * a.n4) return hipErrorInvalidValue;
-  const BinTiles bt = bin_tiles(a.nb);
-  hipLaunchKernelGGL(contract3_kernel<T>, dim3(a.nn * bt.nt * bt.nt, 5, THREE_SLICES), dim3(256), 0, s, a);
+  if (a.lo1 < 0 || a.nb1 < 1 || a.lo1 + a.nb1 > a.nb || a.lo2 < 0 || a.nb2 < 1 || a.lo2 + a.nb2 > a.nb)
+    return hipErrorInvalidValue;
+  const BinTiles bt1 = bin_tiles(a.nb1), bt2 = bin_tiles(a.nb2);
+  hipLaunchKernelGGL(contract3_kernel<T>, dim3(a.nn * bt1.nt * bt2.nt, 5, THREE_SLICES), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(diag3_kernel<T>, dim3(5, THREE_SLICES, bt.nt), dim3(256), 0, s, a);
+  // the same-neighbour sums exist where both slots share bins and records
+  if (a.lo1 == a.lo2 && a.nb1 == a.nb2 && a.rec2 == a.rec && a.par1 == nullptr && a.par2 == nullptr)
+    hipLaunchKernelGGL(diag3_kernel<T>, dim3(5, THREE_SLICES, bt1.nt), dim3(256), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t elems2 = 2 * three_elems(a.nb, a.m);

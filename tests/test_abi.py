@@ -213,3 +213,18 @@ def test_valid_host_out_is_filled_in_place():
     out = np.full(m.output_shape(2, 1), 7 + 7j)
     got = m.estimate_4pcf_multipoles(x, x, x, x, x + 1, [1.0, 2.0, 4.0], 1, out=out)
     assert got is out and not np.any(out)
+
+
+def test_basetree_rejects_centre_subsets_and_fp64():
+    import paper_2509_07974_amd as fp
+    x = np.arange(10.0)
+    for kw, code in (({"centers": [1, 2]}, -1), ({"precision": "fp64"}, -2)):
+        kw.setdefault("precision", "fp16")
+        with pytest.raises(fp.Fpcf4Error) as ei:
+            fp.estimate_3pcf_multipoles(x, x, x * 0, x * 0, x * 0 + 1, [1.0, 2.0, 4.0], 2,
+                                        base=(0.5, 2, 4.0), **kw)
+        assert ei.value.status == code
+    with pytest.raises(fp.Fpcf4Error) as ei:
+        fp.estimate_3pcf_multipoles(x, x, x * 0, x * 0, x * 0 + 1, [1.0, 2.0, 4.0], 2,
+                                    precision="fp16", base=(0.5, 9, 4.0))
+    assert ei.value.status == -1
