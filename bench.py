@@ -375,26 +375,28 @@ def threepcf_report(fp, dev, n, edges, precision, no_fp64):
                                  "contraction_and_same_neighbour": prof["stage_b_ms"] / 2}}
     log(f"3pcf: {dt:.3f} s/step")
     if precision != "fp64":
-        # BaseTree: base points on grids of 0.5', 1', 2' (r_min 40, the tree
-        # setting of the paper's survey measurement)
-        def run_bt():
-            return fp.estimate_3pcf_multipoles(*dev, edges, THREEPCF_NMAX, precision=precision, base=BASETREE)
-        run_bt()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(2):
-            bto = run_bt()
-        torch.cuda.synchronize()
-        dbt = (time.perf_counter() - t) / 2
-        a, b = bto.cpu().numpy(), out.cpu().numpy()
-        rep["basetree"] = {
-            "delta1": BASETREE[0], "levels": BASETREE[1], "rmin": BASETREE[2],
-            "bin_grids": grid_levels(edges, *BASETREE),
-            "ms_per_step": dbt * 1e3, "value": n / dbt, "unit": "centres/s",
-            "speedup_vs_discrete": dt / dbt,
-            "deviation_from_discrete_per_mu": [float(np.linalg.norm(a[m] - b[m]) / np.linalg.norm(b[m]))
-                                               for m in range(5)]}
-        log(f"3pcf basetree: {dbt:.3f} s/step ({dt / dbt:.2f}x)")
+        # BaseTree (base points on grids of 0.5', 1', 2', r_min 40, the tree
+        # setting of the paper's survey measurement) and DoubleTree (the
+        # neighbours on the same grids as well)
+        for key, kw in (("basetree", {"base": BASETREE}), ("doubletree", {"base": BASETREE, "tree": BASETREE})):
+            def run_bt():
+                return fp.estimate_3pcf_multipoles(*dev, edges, THREEPCF_NMAX, precision=precision, **kw)
+            run_bt()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(2):
+                bto = run_bt()
+            torch.cuda.synchronize()
+            dbt = (time.perf_counter() - t) / 2
+            a, b = bto.cpu().numpy(), out.cpu().numpy()
+            rep[key] = {
+                "delta1": BASETREE[0], "levels": BASETREE[1], "rmin": BASETREE[2],
+                "bin_grids": grid_levels(edges, *BASETREE),
+                "ms_per_step": dbt * 1e3, "value": n / dbt, "unit": "centres/s",
+                "speedup_vs_discrete": dt / dbt,
+                "deviation_from_discrete_per_mu": [float(np.linalg.norm(a[m] - b[m]) / np.linalg.norm(b[m]))
+                                                   for m in range(5)]}
+            log(f"3pcf {key}: {dbt:.3f} s/step ({dt / dbt:.2f}x)")
     if not no_fp64 and precision != "fp64":
         run("fp64")
         torch.cuda.synchronize()

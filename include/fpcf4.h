@@ -196,28 +196,37 @@ fpcf4_status estimate_4pcf_multipoles_tree(const fpcf4_catalogue *cat,
                                            const fpcf4_tree *tree,
                                            double *upsilon, int32_t out_mem);
 
-/* Shear 3PCF multipoles (as estimate_3pcf_multipoles) with the BaseTree
- * approximation of the appendix on N-th order statistics (its subsection on
- * the algorithmic implementation): the base points X_0 are the pseudo-
- * galaxies of a hierarchy of grids of cell side base->delta1 * 2^(d-1),
- * d = 1..base->nlevels (anchored, centred and summed as for the tree
- * approximation), each carrying the cell sums of w gamma and w as its centre
- * value; radial bin b uses the coarsest grid with
- * edges[b] / Delta_d >= base->rmin, or the galaxies when none qualifies.
- * For a bin pair the centre value times the block of the bin on the finer
- * grid is summed over the cells of that grid inside each cell of the coarser
- * grid (cells are nested) and multiplied there by the other bin's block.
- * The same-neighbour terms are removed where Theta_1 = Theta_2.  With no
- * bin reaching a grid the result equals estimate_3pcf_multipoles.
- * Mixed precisions only (FPCF4_E_UNSUPPORTED for FPCF4_FP64); every galaxy
- * is a base point (FPCF4_E_INVALID_ARG for opts->centers); the records of
- * all galaxies must fit one centre tile (FPCF4_E_UNSUPPORTED otherwise).
- * Output and other errors as estimate_3pcf_multipoles. */
-fpcf4_status estimate_3pcf_multipoles_basetree(const fpcf4_catalogue *cat,
-                                               const fpcf4_bins *bins,
-                                               const fpcf4_options *opts,
-                                               const fpcf4_tree *base,
-                                               double *upsilon3, int32_t out_mem);
+/* Shear 3PCF multipoles (as estimate_3pcf_multipoles) with the BaseTree and
+ * Tree approximations of the appendix on N-th order statistics (its
+ * subsection on the algorithmic implementation); both together are the
+ * DoubleTree approximation.
+ * base (may be NULL): the base points X_0 are the pseudo-galaxies of a
+ *   hierarchy of grids of cell side base->delta1 * 2^(d-1), d = 1 ..
+ *   base->nlevels (anchored, centred and summed as for the tree
+ *   approximation, fpcf4_tree below), each carrying the cell sums of w gamma
+ *   and w as its centre value; radial bin b uses the coarsest grid with
+ *   edges[b] / Delta_d >= base->rmin, or the galaxies when none qualifies.
+ *   For a bin pair the centre value times the block of the bin on the finer
+ *   grid is summed over the cells of that grid inside each cell of the
+ *   coarser grid (cells are nested) and multiplied there by the other bin's
+ *   block.  Every galaxy is a base point (FPCF4_E_INVALID_ARG for
+ *   opts->centers) and the records of all galaxies must fit one centre tile
+ *   (FPCF4_E_UNSUPPORTED otherwise).
+ * tree (may be NULL): the blocks of radial bin b are allocated over the
+ *   pseudo-galaxies of the coarsest neighbour grid with
+ *   edges[b] / Delta_d >= tree->rmin (as in estimate_4pcf_multipoles_tree),
+ *   with the cell sums of the product weights in the same-neighbour terms.
+ * The same-neighbour terms are removed where Theta_1 = Theta_2.  With no bin
+ * reaching a grid of either hierarchy the result equals
+ * estimate_3pcf_multipoles.  Mixed precisions only when base or tree is
+ * given (FPCF4_E_UNSUPPORTED for FPCF4_FP64).  Output and other errors as
+ * estimate_3pcf_multipoles. */
+fpcf4_status estimate_3pcf_multipoles_doubletree(const fpcf4_catalogue *cat,
+                                                 const fpcf4_bins *bins,
+                                                 const fpcf4_options *opts,
+                                                 const fpcf4_tree *base,
+                                                 const fpcf4_tree *tree,
+                                                 double *upsilon3, int32_t out_mem);
 
 /* Stage (a) only, for parity checks (Sect. 3.1: the per-centre blocks G_n and
  * W_n "defined as in P24", read as G_k = sum_j w_j gamma_j e^{+ik phi_ij} and

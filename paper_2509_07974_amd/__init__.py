@@ -203,20 +203,21 @@ def estimate_4pcf_multipoles_noalloc(x, y, g1, g2, w, edges, nmax: int, precisio
 
 def estimate_3pcf_multipoles(x, y, g1, g2, w, edges, nmax: int, precision="fp64",
                              subtract_degenerate: bool = True, centers=None,
-                             tile_centers: int = 0, stream=None, out=None, base=None):
+                             tile_centers: int = 0, stream=None, out=None, base=None, tree=None):
     """Shear 3PCF multipoles Upsilon_{mu,n}(T1,T2), mu = 0..3, and N (index 4)
     as a complex128 array [5, nb, nb, 2nmax+1] (NumPy for host inputs, a
     torch tensor on the inputs' device for device inputs).  nmax <= 32.
     base = (delta1, nlevels, rmin) selects the BaseTree approximation of the
-    base points (grids delta1 * 2^(d-1); mixed precisions, every galaxy a
-    base point)."""
+    base points (grids delta1 * 2^(d-1); every galaxy a base point),
+    tree = (delta1, nlevels, rmin) the tree approximation of the neighbours;
+    both together are the DoubleTree (mixed precisions only)."""
     m = _Marshal(x, y, g1, g2, w, edges, nmax, precision, subtract_degenerate, centers,
                  tile_centers, stream)
     res, ptr, mem = m.output(output3_shape(m.nbins, m.nmax), out)
-    if base is not None:
-        delta1, nlevels, rmin = base
-        t = _lib.Tree(int(nlevels), 0, float(delta1), float(rmin))
-        check(lib().estimate_3pcf_multipoles_basetree(*m.refs(), C.byref(t), C.c_void_p(ptr), mem))
+    if base is not None or tree is not None:
+        def tr(t):
+            return None if t is None else C.byref(_lib.Tree(int(t[1]), 0, float(t[0]), float(t[2])))
+        check(lib().estimate_3pcf_multipoles_doubletree(*m.refs(), tr(base), tr(tree), C.c_void_p(ptr), mem))
     else:
         check(lib().estimate_3pcf_multipoles(*m.refs(), C.c_void_p(ptr), mem))
     return res

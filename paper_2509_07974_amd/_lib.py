@@ -116,9 +116,9 @@ def lib():
     L.estimate_4pcf_multipoles_tree.restype = C.c_int32
     L.estimate_4pcf_multipoles_noalloc.argtypes = [P(Catalogue), P(Bins), P(Options), C.c_void_p, C.c_int32]
     L.estimate_4pcf_multipoles_noalloc.restype = C.c_int32
-    L.estimate_3pcf_multipoles_basetree.argtypes = [P(Catalogue), P(Bins), P(Options), P(Tree), C.c_void_p,
-                                                    C.c_int32]
-    L.estimate_3pcf_multipoles_basetree.restype = C.c_int32
+    L.estimate_3pcf_multipoles_doubletree.argtypes = [P(Catalogue), P(Bins), P(Options), P(Tree), P(Tree),
+                                                      C.c_void_p, C.c_int32]
+    L.estimate_3pcf_multipoles_doubletree.restype = C.c_int32
     _lib = L
     return L
 
@@ -134,5 +134,5 @@ EXPORTED = [
     "fpcf4_request_destroy", "fpcf4_last_error", "fpcf4_version", "fpcf4_output_elems",
     "fpcf4_profile_enable", "fpcf4_profile_read", "estimate_3pcf_multipoles", "fpcf4_output3_elems",
     "fpcf4_to_natural_triplets", "estimate_4pcf_multipoles_tree", "estimate_4pcf_multipoles_noalloc",
-    "estimate_3pcf_multipoles_basetree",
+    "estimate_3pcf_multipoles_doubletree",
 ]

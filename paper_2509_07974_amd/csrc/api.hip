@@ -969,27 +969,29 @@ fpcf4_status estimate_3pcf_multipoles(const fpcf4_catalogue* cat, const fpcf4_bi
   return st;
 }
 
-fpcf4_status estimate_3pcf_multipoles_basetree(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
-                                               const fpcf4_options* opts, const fpcf4_tree* base,
-                                               double* upsilon3, int32_t out_mem) {
-  if (!upsilon3 || !opts || !base) return fail(FPCF4_E_INVALID_ARG, "null argument");
+fpcf4_status estimate_3pcf_multipoles_doubletree(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
+                                                 const fpcf4_options* opts, const fpcf4_tree* base,
+                                                 const fpcf4_tree* tree, double* upsilon3, int32_t out_mem) {
+  if (!upsilon3 || !opts) return fail(FPCF4_E_INVALID_ARG, "null argument");
   if (out_mem != FPCF4_MEM_HOST && out_mem != FPCF4_MEM_DEVICE) return fail(FPCF4_E_INVALID_ARG, "out_mem %d", out_mem);
   if (opts->nmax < 0) return fail(FPCF4_E_INVALID_ARG, "nmax < 0");
   if (opts->nmax > FPCF4_NMAX3_SUPPORTED)
     return fail(FPCF4_E_UNSUPPORTED, "3PCF nmax %d > %d", opts->nmax, FPCF4_NMAX3_SUPPORTED);
-  fpcf4_status st = check_tree(base, "base");
-  if (st != FPCF4_OK) return st;
-  if (opts->precision == FPCF4_FP64)
-    return fail(FPCF4_E_UNSUPPORTED, "the BaseTree approximation runs in the mixed paths only");
-  if (opts->centers) return fail(FPCF4_E_INVALID_ARG, "BaseTree: every galaxy is a base point (no centre subset)");
+  fpcf4_status st = FPCF4_OK;
+  if (base && (st = check_tree(base, "base")) != FPCF4_OK) return st;
+  if (tree && (st = check_tree(tree, "tree")) != FPCF4_OK) return st;
+  if ((base || tree) && opts->precision == FPCF4_FP64)
+    return fail(FPCF4_E_UNSUPPORTED, "the tree approximations run in the mixed paths only");
+  if (base && opts->centers)
+    return fail(FPCF4_E_INVALID_ARG, "BaseTree: every galaxy is a base point (no centre subset)");
   const int m = opts->nmax;
   fpcf4_options o = *opts;
   o.nmax = (m + 1) / 2;
-  o.tile_centers = 0;
+  if (base) o.tile_centers = 0;
   PlanInfo P;
-  st = make_plan(cat, bins, &o, P, 3, m);
+  st = make_plan(cat, bins, &o, P, 3, m, tree);
   if (st != FPCF4_OK) return st;
-  if (P.ntiles > 1)
+  if (base && P.ntiles > 1)
     return fail(FPCF4_E_UNSUPPORTED, "BaseTree: the records of all %lld galaxies must fit one tile",
                 (long long)P.n);
   setup_pool();
@@ -998,8 +1000,13 @@ fpcf4_status estimate_3pcf_multipoles_basetree(const fpcf4_catalogue* cat, const
   HIPCHK(hipMallocAsync(&ws, P.total, s));
   fpcf4_request* R = new (std::nothrow) fpcf4_request();
   if (!R) st = fail(FPCF4_E_OUT_OF_MEMORY, "host allocation failed");
-  if (st == FPCF4_OK) st = request_init(cat, bins, &o, ws, P.total, R, 3, m);
-  if (st == FPCF4_OK && P.n > 0) st = run_3pcf_basetree(R, cat, bins, base);
+  if (st == FPCF4_OK) st = request_init(cat, bins, &o, ws, P.total, R, 3, m, tree);
+  if (base) {
+    if (st == FPCF4_OK && P.n > 0) st = run_3pcf_basetree(R, cat, bins, base);
+  } else {
+    // neighbours on the tree's grids, base points the galaxies: the tiled path
+    for (int64_t t = 0; st == FPCF4_OK && t < P.ntiles; ++t) st = request_step(R, t, true);
+  }
   if (st == FPCF4_OK) st = fpcf4_request_finalize(R, upsilon3, out_mem);
   delete R;
   hipError_t e = hipFreeAsync(ws, s);

@@ -1048,12 +1048,12 @@ hipError_t launch_n(const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t
   if (e != hipSuccess) return e;
   *nlaunch = 1;
   if (red) {
-    if constexpr (sizeof(T) == 4 && !is3(N)) {
+    if constexpr (sizeof(T) == 4) {
       ar.work_counter = a.work_counter + 8;
       if ((e = launch_pairs<T, N, true>(ar, s)) != hipSuccess) return e;
       *nlaunch = 2;
     } else {
-      return hipErrorInvalidValue;   // reduced catalogues: binary32 4PCF only
+      return hipErrorInvalidValue;   // reduced catalogues: binary32 only
     }
   }
   if (mid != nullptr && (e = hipEventRecord(mid, s)) != hipSuccess) return e;

@@ -1,8 +1,9 @@
-"""GPU parity of the BaseTree approximation of the shear 3PCF (App. F.3,
-algorithmic implementation) against its FP64 oracle, through the C ABI
-(mixed paths; the bars of helpers.assert_parity without the term-scale bar:
-the discrete catalogue's absolute sums do not bound the pseudo-galaxy
-terms), and the limit in which it equals the discrete 3PCF."""
+"""GPU parity of the BaseTree, Tree and DoubleTree approximations of the
+shear 3PCF (App. F.3, algorithmic implementation) against their FP64
+oracle, through the C ABI (mixed paths; the bars of helpers.assert_parity
+without the term-scale bar: the discrete catalogue's absolute sums do not
+bound the pseudo-galaxy terms), and the limit in which they equal the
+discrete 3PCF."""
 import functools
 
 import numpy as np
@@ -16,6 +17,7 @@ from helpers import assert_parity, rel_per_mu
 pytestmark = pytest.mark.gpu
 M3 = 6
 BASE = (0.5, 2, 4.0)      # grids 0.5' and 1': the four 1-30' bins -> [0, 1, 2, 2]
+TREE = (0.4, 2, 5.0)      # neighbour grids 0.4' and 0.8': -> [0, 1, 2, 2]
 
 
 @pytest.fixture(scope="module")
@@ -32,9 +34,10 @@ def c0(nb=4):
 
 
 @functools.lru_cache(None)
-def c0_ref(nb=4, distinct=True):
+def c0_ref(nb=4, distinct=True, mode="base"):
     cat, edges = c0(nb)
-    return bt.upsilon3_doubletree(*cat.arrays(), edges, M3, base=BASE, distinct=distinct)
+    kw = {"base": {"base": BASE}, "tree": {"tree": TREE}, "double": {"base": BASE, "tree": TREE}}[mode]
+    return bt.upsilon3_doubletree(*cat.arrays(), edges, M3, distinct=distinct, **kw)
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
@@ -78,3 +81,30 @@ def test_basetree_device_inputs_match_host(fp):
     dev = [torch.from_numpy(a).cuda() for a in cat.arrays()]
     got = fp.estimate_3pcf_multipoles(*dev, edges, M3, precision="fp16", base=BASE)
     assert np.all(rel_per_mu(got.cpu().numpy(), host) < 1e-14)
+
+
+@pytest.mark.parametrize("mode", ["tree", "double"])
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_tree_and_doubletree_c0_match_oracle(fp, mode, prec):
+    cat, edges = c0()
+    assert oracle.tree_levels(edges, *TREE) == [0, 1, 2, 2]
+    kw = {"tree": {"tree": TREE}, "double": {"base": BASE, "tree": TREE}}[mode]
+    got = fp.estimate_3pcf_multipoles(*cat.arrays(), edges, M3, precision=prec, **kw)
+    assert_parity(got, c0_ref(4, True, mode), prec, nbin=2, label=f"{mode} c0")
+    raw = fp.estimate_3pcf_multipoles(*cat.arrays(), edges, M3, precision=prec, subtract_degenerate=False, **kw)
+    assert_parity(raw, c0_ref(4, False, mode), prec, nbin=2, label=f"{mode} c0 raw")
+
+
+def test_tree_3pcf_tiles_and_subsets(fp):
+    """The tree alone keeps the tiled path: tiles add up, and a centre subset
+    is the sum over those centres (additivity against the complement)."""
+    cat, edges = c0()
+    one = fp.estimate_3pcf_multipoles(*cat.arrays(), edges, M3, precision="fp16", tree=TREE)
+    many = fp.estimate_3pcf_multipoles(*cat.arrays(), edges, M3, precision="fp16", tree=TREE,
+                                       tile_centers=333)
+    assert np.all(rel_per_mu(many, one) < 1e-6)
+    idx = np.arange(0, cat.n, 3)
+    rest = np.setdiff1d(np.arange(cat.n), idx)
+    a = fp.estimate_3pcf_multipoles(*cat.arrays(), edges, M3, precision="fp16", tree=TREE, centers=idx)
+    b = fp.estimate_3pcf_multipoles(*cat.arrays(), edges, M3, precision="fp16", tree=TREE, centers=rest)
+    assert np.all(rel_per_mu(a + b, one) < 1e-6)
