@@ -209,3 +209,54 @@ def test_65_bins_counts(fp):
     counts, _, _ = fp.debug_multipoles(*cat.arrays(), edges, nmax, precision="fp16", centers=idx)
     assert np.array_equal(counts, oracle.bin_counts(cat.x, cat.y, edges, idx))
     assert (counts[:, 30:] > 0).all()
+
+
+# --------------------------------------------------------------------------
+# the largest bin count
+# --------------------------------------------------------------------------
+NBMAX = 128
+
+
+@functools.lru_cache(None)
+def cmax():
+    """uniform-2k with 128 log bins over 5-30' (8 tiles of 16 bins), nmax 2,
+    200 seeded centres, 160 sampled triplets (random, coincident, tile edges)."""
+    cat, _, _, _ = synth.workload("uniform-2k")
+    edges = synth.log_edges(5.0, 30.0, NBMAX)
+    rng = np.random.default_rng(49)
+    idx = np.sort(rng.choice(cat.n, 200, replace=False))
+    t = [tuple(r) for r in rng.integers(0, NBMAX, size=(120, 3))]
+    for a, b in ((15, 16), (63, 64), (0, 127)):
+        t += [(a, a, b), (a, b, a), (b, a, a), (a, a, a), (b, b, b)]
+    t += [tuple(rng.choice([0, 15, 16, 31, 32, 111, 112, 127], 3)) for _ in range(25)]
+    t = np.array(t, dtype=np.int64)
+    ref = oracle.upsilon_triplets_parallel(*cat.arrays(), edges, 2, t, idx, processes=PROCS)
+    S = oracle.abs_bound(*cat.arrays(), edges, idx)
+    return cat, edges, idx, t, ref, S[:, t[:, 0], t[:, 1], t[:, 2]]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_max_bins_sampled(fp, prec):
+    import torch
+    cat, edges, idx, t, ref, S = cmax()
+    assert np.abs(ref).max() > 0
+    dev = [torch.as_tensor(a, device="cuda") for a in cat.arrays()]
+    got = fp.estimate_4pcf_multipoles(*dev, edges, 2, precision=prec, centers=idx)
+    assert tuple(got.shape) == (9, NBMAX, NBMAX, NBMAX, 5, 5)
+    sel = pick(got, t)
+    del got
+    torch.cuda.empty_cache()
+    eq = (t[:, 0] == t[:, 1]) | (t[:, 0] == t[:, 2]) | (t[:, 1] == t[:, 2])
+    assert_parity(sel, ref, prec, S, label="128 bins sampled triplets", eq=eq)
+
+
+def test_max_bins_3pcf(fp):
+    cat, edges, idx, _, _, _ = cmax()
+    c = synth.subset(cat, np.random.default_rng(50).choice(cat.n, 300, replace=False))
+    ref = oracle.upsilon3(*c.arrays(), edges, 4)
+    S = oracle.abs_bound(*c.arrays(), edges, order=3)
+    for prec in ("fp64", "fp16"):
+        got = fp.estimate_3pcf_multipoles(*c.arrays(), edges, 4, precision=prec)
+        assert_parity(got, ref, prec, S, nbin=2, label="3pcf 128 bins")
+    with pytest.raises(fp.Fpcf4Error):
+        fp.estimate_3pcf_multipoles(*c.arrays(), synth.log_edges(5.0, 30.0, NBMAX + 1), 4, precision="fp16")
