@@ -264,16 +264,20 @@ def c4_report(precision: str):
             "generation_s": gen}
 
 
-def stage_b_roofline(ncent, nb, nmax, precision, ms, issued):
-    """MFMA roofline of the contraction: useful flops (8 per complex
-    multiply-add, 9 nb^3 (2nmax+1)^2 per centre) and the matrix-core flops
-    the library reports it issued (padding, surplus tiles and the three hi/lo
-    products of the 16-bit paths included), over the measured stage time."""
+def stage_b_roofline(ncent, nb, nmax, precision, ms, issued, useful):
+    """MFMA roofline of the contraction over the measured stage time: useful
+    flops (8 per complex multiply-add of the distinct block products the
+    library formed: each product of three blocks once, over all bin
+    triples), the matrix-core flops it issued (padding, surplus tiles and
+    the three hi/lo products of the 16-bit paths included), and the rate of
+    one dense contraction per (mu, n2, n3) giving the same outputs in the
+    same time (8 flop x 9 nb^3 (2nmax+1)^2 per centre)."""
     nn = 2 * nmax + 1
-    useful = 8.0 * 9 * nb ** 3 * nn * nn * ncent
+    dense = 8.0 * 9 * nb ** 3 * nn * nn * ncent
     peak = PEAK_FP64_MFMA if precision == "fp64" else PEAK_F16_MFMA
     t = ms * 1e-3
     return {"bound": "mfma", "useful_tflops": useful / t / 1e12, "issued_tflops": issued / t / 1e12,
+            "dense_equivalent_tflops": dense / t / 1e12,
             "peak": peak / 1e12, "unit": "TFLOP/s", "frac_issued": issued / t / peak,
             "frac_useful": useful / t / peak, "stage_ms": ms}
 
@@ -505,7 +509,8 @@ def main():
              "generation_s": gen_s,
              "roofline_stage_b": stage_b_roofline(cat.n, len(edges) - 1, nmax, args.precision,
                                                   prof["stage_b_ms"] / steps,
-                                                  prof["stage_b_mfma_flops"] / steps)}
+                                                  prof["stage_b_mfma_flops"] / steps,
+                                                  prof["stage_b_useful_flops"] / steps)}
     log(f"timed {args.steps} steps: {dt:.3f} s/step")
     if not args.no_fp64 and args.precision != "fp64":
         ref = run("fp64")

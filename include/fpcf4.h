@@ -328,6 +328,9 @@ typedef struct {
   int64_t stage_a_launches, stage_b_launches, steps, pairs, centres;
   double stage_b_mfma_flops;  /* matrix-core flops the contraction issued
                                  (padding and hi/lo products included)    */
+  double stage_b_useful_flops; /* 8 per complex multiply-add of the distinct
+                                  block products it formed (every bin
+                                  triple of every distinct product)       */
 } fpcf4_profile;
 
 /* Enable (on != 0) or disable timing; either call resets the totals. */

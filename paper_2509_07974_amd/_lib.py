@@ -51,7 +51,7 @@ class Profile(C.Structure):
                 ("stage_b_ms", C.c_double), ("corr_ms", C.c_double),
                 ("stage_a_launches", C.c_int64), ("stage_b_launches", C.c_int64),
                 ("steps", C.c_int64), ("pairs", C.c_int64), ("centres", C.c_int64),
-                ("stage_b_mfma_flops", C.c_double)]
+                ("stage_b_mfma_flops", C.c_double), ("stage_b_useful_flops", C.c_double)]
 
 
 class Fpcf4Error(RuntimeError):

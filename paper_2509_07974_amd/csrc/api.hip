@@ -275,7 +275,7 @@ struct fpcf4_request {
   bool no_events = false;       // allocation-free path: never create profiling events
   std::vector<hipEvent_t> ev;   // 4 per profiled step
   int64_t prof_a_launches = 0, prof_b_launches = 0, prof_steps = 0, prof_centres = 0;
-  double prof_b_flops = 0.0;
+  double prof_b_flops = 0.0, prof_b_useful = 0.0;
   ~fpcf4_request() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
@@ -509,6 +509,7 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
     if (prof) {
       HIPCHK(hipEventRecord(evs[4], s));
       R->prof_b_flops += pair_issued_flops(R->pplan, P.nb, ncent, P.precision);
+      R->prof_b_useful += pair_useful_flops(R->pplan, P.nb, ncent);
       R->prof_a_launches += nlaunch;
       R->prof_b_launches += R->pplan.cls_count[1] > 0 && R->pplan.cls_count[2] > 0 ? 3 : 2;
       R->prof_steps += 1;
@@ -838,6 +839,7 @@ fpcf4_status fpcf4_request_finalize(fpcf4_request* req, double* upsilon, int32_t
     g_prof.pairs += (int64_t)pairs;
     g_prof.centres += req->prof_centres;
     g_prof.stage_b_mfma_flops += req->prof_b_flops;
+    g_prof.stage_b_useful_flops += req->prof_b_useful;
   }
   return FPCF4_OK;
 }

@@ -198,7 +198,9 @@ struct PairItem {
   PairRow blk[PAIR_MAX_BLK];
 };
 struct PairOut {                   // where (mu, n2, n3) is computed
-  int32_t item, blk, transposed, pad;
+  // perm: bits 2j..2j+1 name which of (b1, b2, b3) supplies the bin of role j
+  // of the item (0: its row block, 1 and 2: its first and second column block)
+  int32_t item, blk, perm, pad;
 };
 struct PairPlanHost {
   std::vector<PairItem> items;     // grouped by row-block count
@@ -238,6 +240,8 @@ struct PairLaunch {
 hipError_t launch_contract_pairs(const PairLaunch& pl, hipStream_t s);
 // matrix-core flops the pair contraction issues for ncent centres
 double pair_issued_flops(const PairPlanHost& pp, int nb, int64_t ncent, int precision);
+// 8 flop per complex multiply-add of the distinct products: row blocks x nb^3
+double pair_useful_flops(const PairPlanHost& pp, int nb, int64_t ncent);
 size_t corr_elems(int nb, int nmax);  // complex elements of the correction buffer
 hipError_t launch_finalize(const double* ups_raw, const double* corr, int nb, int nmax,
                            int subtract, double* out, hipStream_t s);

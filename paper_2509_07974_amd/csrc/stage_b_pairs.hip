@@ -1,5 +1,5 @@
-// Stage (b) of the mixed-precision paths on the matrix cores, organised by
-// the pair of blocks at Theta_2 and Theta_3 (Sect. 3.1):
+// Stage (b) on the matrix cores (every precision), organised by pairs of
+// blocks whose Khatri-Rao product is formed once (Sect. 3.1):
 //
 //   Upsilon_mu[b1,b2,b3; n2,n3] = sum_i (x A)_i(b1) * B_i(b2) C_i(b3),
 //
@@ -9,20 +9,24 @@
 // operand, the Khatri-Rao product R(b2,b3) = B(b2) C(b3), has to be formed on
 // the vector ALUs; the left operand y(b1) = x A(b1) is a per-centre vector.
 //
-// Many (mu, n2, n3) share the same R: the factor table of Sect. 3.1 uses only
-// G_k (plain or conjugated) and W_k, so every B C product is one of a few
-// kinds of block pairs with two orders, e.g. G_p(b2) G_q(b3) is the R of
-// mu = 0, 2 at (n2, n3) = (-p-2, -q-3) and of mu = 1, 5 at (-p-2, -q-1).
-// The Theta_2 <-> Theta_3 relation of Table 2 (the (Theta_1, Theta_3,
-// Theta_2) column) is the same statement for the transposed pair:
-// G_p(b2) G_q(b3) = G_q(b3) G_p(b2) read with b2 and b3 exchanged.  The host
-// plan (make_pair_plan) therefore lists every distinct unordered pair of
-// (family, conjugation, order) once as a work item; its rows are the distinct
-// left factors (x kind, A family, A conjugation, A order) of every (mu, n2,
-// n3) that uses the pair, in either orientation; and an output map sends each
-// (mu, n2, n3) to (item, row block, transposed).  At nmax = 10 this forms
-// 1029 pairs instead of 7 * 441 and issues half the MFMA work of one GEMM
-// per (mu group, n2, n3).
+// Many (mu, n2, n3) need the same product of three blocks.  Upsilon is a
+// sum over centres of x times a block at each of the three bins, and which
+// block is called the one at Theta_1, 2 or 3 is only a labelling of those
+// bins: if the blocks (A, B, C) of one (mu, n2, n3) are a permutation of the
+// blocks (D, E, F) of another (same x), then its Upsilon[b1, b2, b3] is the
+// other's sum read at the correspondingly permuted bins.  This is the
+// radial symmetry of Sect. 3.1 and Table 2 (a correlator at permuted radii
+// is another correlator at other multipoles) taken at the level of the
+// blocks, and it holds for every (n2, n3) in range, so no extended multipole
+// range is needed.  The factor table uses only G_k (plain or conjugated) and
+// W_k, so the 9 (2nmax+1)^2 products reduce to 1121 distinct multisets of
+// three blocks (with x) at nmax = 10.  The host plan (make_pair_plan) covers
+// them with few column pairs: a work item is an unordered pair (E, F) whose
+// Khatri-Rao product R(c2, c3) = E(c2) F(c3) is formed once, over all bins;
+// its rows are the third blocks x D(c1) of the multisets assigned to it.  An
+// output map sends each (mu, n2, n3) to (item, row block, permutation of
+// (b1, b2, b3) into (c1, c2, c3)).  At nmax = 10: 665 work items and 1121
+// row blocks, against 3969 (mu, n2, n3) GEMMs of one row block each.
 //
 // Per work item and centre slice, one workgroup of W waves: a chunk of 32
 // centres is staged in LDS as B and C rows (binary32 complex, power-of-two
@@ -38,9 +42,10 @@
 // binary64 (unscaled exactly) and written into the workgroup's own region of
 // the slice partial buffer (the first sub-slice stores, later ones add: the
 // same lanes read back what they wrote).  pair_reduce_kernel adds the slices
-// in order and scatters every (mu, n2, n3) from its item and orientation into
-// the output tensor.  No atomics: the result is deterministic.
+// in order and scatters every (mu, n2, n3) from its item and permutation
+// into the output tensor.  No atomics: the result is deterministic.
 #include <algorithm>
+#include <array>
 #include <map>
 #include <tuple>
 #include <type_traits>
@@ -56,50 +61,131 @@ namespace fpcf4 {
 // ---------------------------------------------------------------------------
 PairPlanHost make_pair_plan(int nmax, int nb) {
   typedef std::tuple<int, int, int> Spec;            // family, conj, order
-  typedef std::tuple<int, int, int, int> RowKey;     // x kind, A family, A conj, A order
-  struct Tgt { int mu, n2, n3, tr; };
-  std::map<std::pair<Spec, Spec>, std::map<RowKey, std::vector<Tgt>>> items;
+  typedef std::array<Spec, 3> Triple;                // sorted blocks of a product
+  typedef std::pair<int, Triple> Multi;              // (x kind, sorted blocks)
+  typedef std::pair<Spec, Spec> Pair;                // sorted column blocks
+  const int nn = 2 * nmax + 1;
+  // 1. every (mu, n2, n3): its centre factor, the blocks at Theta_1,2,3 and
+  // the multiset they form
+  struct Tuple { int x; Spec s[3]; int ms; };
+  std::vector<Tuple> tup((size_t)FPCF4_NCORR * nn * nn);
+  std::map<Multi, int> ms_id;
   for (int mu = 0; mu < FPCF4_NCORR; ++mu) {
     const MuFactors F = mu_factors(mu);
     for (int n2 = -nmax; n2 <= nmax; ++n2)
       for (int n3 = -nmax; n3 <= nmax; ++n3) {
-        const Spec sb{F.B.fam, F.B.conj, F.B.a * n2 + F.B.b * n3 + F.B.c};
-        const Spec sc{F.C.fam, F.C.conj, F.C.a * n2 + F.C.b * n3 + F.C.c};
-        const bool tr = sc < sb;
-        const std::pair<Spec, Spec> key = tr ? std::make_pair(sc, sb) : std::make_pair(sb, sc);
-        const RowKey rk{F.x, F.A.fam, F.A.conj, F.A.a * n2 + F.A.b * n3 + F.A.c};
-        items[key][rk].push_back({mu, n2, n3, tr ? 1 : 0});
+        Tuple& t = tup[((size_t)mu * nn + (n2 + nmax)) * nn + (n3 + nmax)];
+        t.x = F.x;
+        t.s[0] = Spec{F.A.fam, F.A.conj, F.A.a * n2 + F.A.b * n3 + F.A.c};
+        t.s[1] = Spec{F.B.fam, F.B.conj, F.B.a * n2 + F.B.b * n3 + F.B.c};
+        t.s[2] = Spec{F.C.fam, F.C.conj, F.C.a * n2 + F.C.b * n3 + F.C.c};
+        Triple m{t.s[0], t.s[1], t.s[2]};
+        std::sort(m.begin(), m.end());
+        ms_id.emplace(Multi{t.x, m}, 0);
       }
   }
+  std::vector<Multi> ms;
+  for (auto& kv : ms_id) {
+    kv.second = (int)ms.size();
+    ms.push_back(kv.first);
+  }
+  for (Tuple& t : tup) {
+    Triple m{t.s[0], t.s[1], t.s[2]};
+    std::sort(m.begin(), m.end());
+    t.ms = ms_id.at(Multi{t.x, m});
+  }
+  // the (up to three) pairs each multiset can be formed from, ids in pair order
+  std::map<Pair, int> pair_id;
+  for (const Multi& m : ms)
+    for (int i = 0; i < 3; ++i) pair_id.emplace(Pair{m.second[i == 0 ? 1 : 0], m.second[i == 2 ? 1 : 2]}, 0);
+  std::vector<Pair> pairs;
+  for (auto& kv : pair_id) {
+    kv.second = (int)pairs.size();
+    pairs.push_back(kv.first);
+  }
+  std::vector<std::vector<int>> cands(ms.size()), ms_of(pairs.size());
+  for (size_t k = 0; k < ms.size(); ++k)
+    for (int i = 0; i < 3; ++i) {
+      const int q = pair_id.at(Pair{ms[k].second[i == 0 ? 1 : 0], ms[k].second[i == 2 ? 1 : 2]});
+      if (std::find(cands[k].begin(), cands[k].end(), q) != cands[k].end()) continue;
+      cands[k].push_back(q);
+      ms_of[q].push_back((int)k);
+    }
+  // 2. cover the multisets with few pairs (greedy: the pair that forms the
+  // most uncovered multisets first), then move multisets between chosen
+  // pairs so that fewer pairs carry an odd number of rows (an odd one leaves
+  // a one-block item)
+  std::vector<int> open(pairs.size()), assign(ms.size(), -1), nrows(pairs.size(), 0);
+  for (size_t q = 0; q < pairs.size(); ++q) open[q] = (int)ms_of[q].size();
+  for (size_t left = ms.size(); left > 0;) {
+    const int best = (int)(std::max_element(open.begin(), open.end()) - open.begin());
+    for (int k : ms_of[best]) {
+      if (assign[k] >= 0) continue;
+      assign[k] = best;
+      nrows[best] += 1;
+      --left;
+      for (int q : cands[k]) open[q] -= 1;
+    }
+  }
+  for (bool moved = true; moved;) {                  // each move evens two pairs: terminates
+    moved = false;
+    for (size_t k = 0; k < ms.size(); ++k) {
+      if (nrows[assign[k]] % 2 == 0) continue;
+      for (int q : cands[k])
+        if (q != assign[k] && nrows[q] % 2 == 1) {
+          nrows[assign[k]] -= 1;
+          nrows[q] += 1;
+          assign[k] = q;
+          moved = true;
+          break;
+        }
+    }
+  }
+  // 3. rows of every pair: the block of each multiset that is not in the pair
+  typedef std::tuple<int, int, int, int> RowKey;     // x kind, family, conj, order
+  auto row_spec = [&](int k) {
+    const Pair& q = pairs[assign[k]];
+    std::vector<Spec> rest(ms[k].second.begin(), ms[k].second.end());
+    rest.erase(std::find(rest.begin(), rest.end(), q.first));
+    rest.erase(std::find(rest.begin(), rest.end(), q.second));
+    return rest[0];
+  };
+  std::vector<std::vector<std::pair<RowKey, int>>> rows_of(pairs.size());
+  for (size_t k = 0; k < ms.size(); ++k) {
+    const Spec r = row_spec((int)k);
+    rows_of[assign[k]].push_back({RowKey{ms[k].first, std::get<0>(r), std::get<1>(r), std::get<2>(r)}, (int)k});
+  }
+  // 4. work items of at most PAIR_MAX_BLK row blocks (a pair with more rows
+  // is split over several items that form the same R), grouped by their
+  // number of row blocks (one kernel per class)
   PairPlanHost P;
-  const int nn = 2 * nmax + 1;
   P.out.assign((size_t)FPCF4_NCORR * nn * nn, PairOut{-1, 0, 0, 0});
   for (int c = 0; c <= PAIR_MAX_BLK; ++c) P.cls_start[c] = P.cls_count[c] = 0;
-  // Work items of at most PAIR_MAX_BLK row blocks (a pair used by more left
-  // factors is split over several items that form the same R), grouped by
-  // their number of row blocks (one kernel per class).
-  struct Unit { std::pair<Spec, Spec> key; std::vector<std::pair<RowKey, std::vector<Tgt>>> rows; };
+  struct Unit { int pair; std::vector<std::pair<RowKey, int>> rows; };
   std::vector<Unit> units;
-  for (const auto& kv : items) {
-    std::vector<std::pair<RowKey, std::vector<Tgt>>> all(kv.second.begin(), kv.second.end());
-    for (size_t k = 0; k < all.size(); k += PAIR_MAX_BLK) {
-      Unit u{kv.first, {}};
-      for (size_t q = k; q < all.size() && q < k + PAIR_MAX_BLK; ++q) u.rows.push_back(all[q]);
+  for (size_t q = 0; q < pairs.size(); ++q) {
+    auto& rr = rows_of[q];
+    std::sort(rr.begin(), rr.end());
+    for (size_t k = 0; k < rr.size(); k += PAIR_MAX_BLK) {
+      Unit u{(int)q, {}};
+      for (size_t j = k; j < rr.size() && j < k + PAIR_MAX_BLK; ++j) u.rows.push_back(rr[j]);
       units.push_back(u);
     }
   }
+  std::vector<std::pair<int, int>> where(ms.size());  // multiset -> (item, row block)
   int64_t rows = 0;
   for (int nbk = 1; nbk <= PAIR_MAX_BLK; ++nbk) {
     P.cls_start[nbk] = (int)P.items.size();
     for (const Unit& un : units) {
       if ((int)un.rows.size() != nbk) continue;
+      const Pair& key = pairs[un.pair];
       PairItem it{};
-      it.famB = (int8_t)std::get<0>(un.key.first);
-      it.conjB = (int8_t)std::get<1>(un.key.first);
-      it.ordB = std::get<2>(un.key.first);
-      it.famC = (int8_t)std::get<0>(un.key.second);
-      it.conjC = (int8_t)std::get<1>(un.key.second);
-      it.ordC = std::get<2>(un.key.second);
+      it.famB = (int8_t)std::get<0>(key.first);
+      it.conjB = (int8_t)std::get<1>(key.first);
+      it.ordB = std::get<2>(key.first);
+      it.famC = (int8_t)std::get<0>(key.second);
+      it.conjC = (int8_t)std::get<1>(key.second);
+      it.ordC = std::get<2>(key.second);
       it.nblk = nbk;
       it.row0 = (int32_t)rows;
       for (int k = 0; k < nbk; ++k) {
@@ -108,9 +194,7 @@ PairPlanHost make_pair_plan(int nmax, int nb) {
         it.blk[k].fam = (int8_t)std::get<1>(rk);
         it.blk[k].conj = (int8_t)std::get<2>(rk);
         it.blk[k].order = std::get<3>(rk);
-        for (const Tgt& t : un.rows[k].second)
-          P.out[((size_t)t.mu * nn + (t.n2 + nmax)) * nn + (t.n3 + nmax)] =
-              PairOut{(int32_t)P.items.size(), k, t.tr, 0};
+        where[un.rows[k].second] = {(int)P.items.size(), k};
       }
       rows += (int64_t)nbk * 2 * nb;
       P.items.push_back(it);
@@ -118,6 +202,23 @@ PairPlanHost make_pair_plan(int nmax, int nb) {
     P.cls_count[nbk] = (int)P.items.size() - P.cls_start[nbk];
   }
   P.total_rows = rows;
+  // 5. the output map: (mu, n2, n3) reads its item's region at the bins of
+  // its blocks permuted into the item's (row, column-pair) roles
+  for (size_t o = 0; o < tup.size(); ++o) {
+    const Tuple& t = tup[o];
+    const Pair& q = pairs[assign[t.ms]];
+    const Spec role[3] = {row_spec(t.ms), q.first, q.second};
+    // src[j]: which of (b1, b2, b3) supplies the bin of role j
+    bool used[3] = {false, false, false};
+    int code = 0;
+    for (int j = 0; j < 3; ++j) {
+      int i = 0;
+      while (used[i] || t.s[i] != role[j]) ++i;
+      used[i] = true;
+      code |= i << (2 * j);
+    }
+    P.out[o] = PairOut{where[t.ms].first, where[t.ms].second, code, 0};
+  }
   return P;
 }
 
@@ -728,7 +829,7 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_f64_
 }
 
 // ups[mu][b1][b2][b3][n2][n3] += sum over slices of the item region that holds
-// (mu, n2, n3), read transposed in (b2, b3) where the plan says so
+// (mu, n2, n3), read at (b1, b2, b3) permuted into the item's roles
 __global__ void pair_reduce_kernel(const double* part, int nsl, int64_t slice_elems, const PairItem* items,
                                    const PairOut* out, int nb, int nmax, double* ups) {
   const int nn = 2 * nmax + 1;
@@ -746,8 +847,13 @@ __global__ void pair_reduce_kernel(const double* part, int nsl, int64_t slice_el
     const int b1 = (int)(r % nb); r /= nb;
     const int mu = (int)r;
     const PairOut po = out[((int64_t)mu * nn + n2i) * nn + n3i];
-    const int row = items[po.item].row0 + po.blk * 2 * nb + p * nb + b1;
-    const int col = po.transposed ? b3 * nb + b2 : b2 * nb + b3;
+    // the bins of the item's row block and of its two column blocks
+    const int s0 = po.perm & 3, s1 = (po.perm >> 2) & 3, s2 = (po.perm >> 4) & 3;
+    const int c1 = s0 == 0 ? b1 : s0 == 1 ? b2 : b3;
+    const int c2 = s1 == 0 ? b1 : s1 == 1 ? b2 : b3;
+    const int c3 = s2 == 0 ? b1 : s2 == 1 ? b2 : b3;
+    const int row = items[po.item].row0 + po.blk * 2 * nb + p * nb + c1;
+    const int col = c2 * nb + c3;
     const int64_t src = (int64_t)row * nb * nb + col;
     double v = 0.0;
     for (int k = 0; k < nsl; ++k) v += part[(int64_t)k * slice_elems + src];
@@ -787,6 +893,12 @@ double pair_issued_flops(const PairPlanHost& pp, int nb, int64_t ncent, int prec
          (precision == FPCF4_FP64 ? 1.0 : 3.0);
   }
   return f * (double)ncent * bt.nt * bt.nt * bt.nt;
+}
+
+double pair_useful_flops(const PairPlanHost& pp, int nb, int64_t ncent) {
+  double blocks = 0.0;
+  for (const PairItem& it : pp.items) blocks += it.nblk;
+  return 8.0 * blocks * (double)nb * nb * nb * (double)ncent;
 }
 
 hipError_t launch_contract_pairs(const PairLaunch& pl, hipStream_t s) {
