@@ -243,6 +243,25 @@ fpcf4_status fpcf4_debug_multipoles(const fpcf4_catalogue *cat,
                                     const fpcf4_options *opts,
                                     int64_t *counts, double *G, double *W);
 
+/* The contraction plan of stage (b), for checks (host only: no device work).
+ * Every Upsilon_{mu,(n2,n3)} (Sect. 3.1) is a sum over centres of x times
+ * one block at each of Theta_1, Theta_2, Theta_3; the plan forms each
+ * distinct product of three blocks once, as a row block times a pair of
+ * column blocks, and reads the other (mu, n2, n3) with the same blocks at
+ * permuted bins (the radial symmetry of Table 2).  For every (mu, n2, n3),
+ * in the order of the output tensor, writes 16 int32 to out (host memory,
+ * 9 (2nmax+1)^2 * 16 values):
+ *   [0]      centre factor: 0 = w gamma, 1 = its conjugate, 2 = w
+ *   [1..3]   row block: family (0 = G, 1 = W), conjugated (0/1), order k
+ *   [4..6]   first column block: family, conjugated, order
+ *   [7..9]   second column block: family, conjugated, order
+ *   [10..12] which of (b1, b2, b3) (0, 1, 2) gives the bin of the row block,
+ *            of the first and of the second column block
+ *   [13]     work item, [14] row block within it, [15] row blocks of the item
+ * *nitems (may be NULL) receives the number of work items.
+ * FPCF4_E_INVALID_ARG for nmax outside [0, FPCF4_NMAX_SUPPORTED] or a null out. */
+fpcf4_status fpcf4_debug_pair_plan(int32_t nmax, int32_t *out, int64_t *nitems);
+
 /* Conversion to bin-averaged natural components (Sect. 2.3 and Eq. of the
  * multipole expansion in Sect. 3.1): for nphi linear angular bins on
  * [0, 2pi),

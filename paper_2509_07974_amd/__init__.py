@@ -17,7 +17,7 @@ from ._lib import (FP64, MIXED_FP16, MIXED_BF16, MEM_HOST, MEM_DEVICE, NMAX_SUPP
                    NBINS_SUPPORTED, Fpcf4Error, check, lib)
 
 __all__ = ["estimate_4pcf_multipoles", "estimate_4pcf_multipoles_noalloc", "estimate_3pcf_multipoles",
-           "debug_multipoles", "to_natural",
+           "debug_multipoles", "debug_pair_plan", "to_natural",
            "to_natural_triplets", "natural_blocks", "plan", "Request",
            "profile_enable", "profile_read",
            "PRECISIONS", "Fpcf4Error", "output_shape", "output3_shape", "lib", "version",
@@ -293,6 +293,16 @@ def natural_blocks(upsilon, nphi: int, block: int = 4096, stream=None):
         t = allt[s:s + block]
         gam, nrm = to_natural_triplets(upsilon, nphi, t, stream)
         yield t, gam, nrm
+
+
+def debug_pair_plan(nmax: int):
+    """The stage (b) contraction plan (host only): an int32 array
+    [9, 2nmax+1, 2nmax+1, 16] as fpcf4_debug_pair_plan documents it, and the
+    number of work items."""
+    out = np.zeros((9, 2 * nmax + 1, 2 * nmax + 1, 16), dtype=np.int32)
+    nit = C.c_int64(0)
+    check(lib().fpcf4_debug_pair_plan(int(nmax), out.ctypes.data, C.byref(nit)))
+    return out, int(nit.value)
 
 
 def profile_enable(on: bool = True):

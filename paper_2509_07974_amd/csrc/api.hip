@@ -1016,6 +1016,26 @@ fpcf4_status estimate_3pcf_multipoles_doubletree(const fpcf4_catalogue* cat, con
   return st;
 }
 
+fpcf4_status fpcf4_debug_pair_plan(int32_t nmax, int32_t* out, int64_t* nitems) {
+  if (nmax < 0 || nmax > FPCF4_NMAX_SUPPORTED) return fail(FPCF4_E_INVALID_ARG, "nmax %d outside [0, %d]", nmax,
+                                                          FPCF4_NMAX_SUPPORTED);
+  if (!out) return fail(FPCF4_E_INVALID_ARG, "null out");
+  const PairPlanHost pp = make_pair_plan(nmax, 1);
+  for (size_t o = 0; o < pp.out.size(); ++o) {
+    const PairOut& po = pp.out[o];
+    int32_t* v = out + 16 * o;
+    if (po.item < 0 || po.item >= (int32_t)pp.items.size())
+      return fail(FPCF4_E_DEVICE, "internal: contraction plan leaves an output unassigned");
+    const PairItem& it = pp.items[po.item];
+    const PairRow& r = it.blk[po.blk];
+    const int32_t vals[16] = {r.x, r.fam, r.conj, r.order, it.famB, it.conjB, it.ordB, it.famC, it.conjC, it.ordC,
+                              po.perm & 3, (po.perm >> 2) & 3, (po.perm >> 4) & 3, po.item, po.blk, it.nblk};
+    for (int k = 0; k < 16; ++k) v[k] = vals[k];
+  }
+  if (nitems) *nitems = (int64_t)pp.items.size();
+  return FPCF4_OK;
+}
+
 fpcf4_status fpcf4_debug_multipoles(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
                                     const fpcf4_options* opts_in, int64_t* counts, double* G, double* W) {
   if (!cat || !bins || !opts_in) return fail(FPCF4_E_INVALID_ARG, "null argument");
