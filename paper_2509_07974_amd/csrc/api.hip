@@ -78,10 +78,12 @@ struct PlanInfo {
   // persistent buffers
   size_t o_gal, o_cells, o_centres, o_e2, o_edges, o_counters, o_bbox, o_bad,
       o_pairs, o_part, o_ups, o_corr, o_cpart, o_acc3, o_part3, o_xg, o_xw, o_counts,
-      o_aos, o_region, o_pitems, o_pout, o_ppart;
+      o_aos, o_region, o_pitems, o_pout, o_ppart, o_csums, o_cmap;
   // mixed-precision contraction by Theta_2/Theta_3 block pairs
   int pslices = 0;
   int64_t pitems = 0, prows = 0;
+  // distinct degenerate-term sums
+  int csums = 0, cpair = 0, cmap = 0;
   // tree approximation
   int tree_levels = 0;                      // grids in use (highest level of any bin)
   double tree_delta1 = 0.0;
@@ -203,6 +205,14 @@ fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   P.o_ppart = take((size_t)P.pslices * P.prows * P.nb * P.nb * 8);
   P.o_corr = take(P.corr_bytes);
   P.o_cpart = take(P.corr_bytes * CORR_SLICES);
+  if (pairs) {
+    const CorrPlanHost cp = make_corr_plan(P.nmax);
+    P.csums = (int)cp.sums.size();
+    P.cpair = cp.npair;
+    P.cmap = (int)cp.map.size();
+  }
+  P.o_csums = take((size_t)P.csums * sizeof(CorrSum));
+  P.o_cmap = take((size_t)P.cmap * 4);
   P.o_acc3 = take(P.acc3_bytes);
   P.o_part3 = take(P.acc3_bytes * THREE_SLICES);
   for (int d = 1; d <= P.tree_levels; ++d) {
@@ -271,6 +281,7 @@ struct fpcf4_request {
   Grid grid{};
   std::vector<char> stepped;
   PairPlanHost pplan;           // the pair plan uploaded into the workspace (mixed 4PCF)
+  CorrPlanHost cplan;           // the distinct degenerate-term sums, likewise
   bool want_counts = false;
   bool no_events = false;       // allocation-free path: never create profiling events
   std::vector<hipEvent_t> ev;   // 4 per profiled step
@@ -320,12 +331,18 @@ fpcf4_status request_init(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
     HIPCHK(hipMemcpyAsync(R->ws + P.o_pout, R->pplan.out.data(), R->pplan.out.size() * sizeof(PairOut),
                           hipMemcpyHostToDevice, s));
   }
+  if (P.csums > 0) {
+    R->cplan = make_corr_plan(P.nmax);
+    for (int32_t v : R->cplan.map)
+      if (v < 0 || v >= P.csums) return fail(FPCF4_E_DEVICE, "internal: correction plan leaves a sum unassigned");
+    HIPCHK(hipMemcpyAsync(R->ws + P.o_csums, R->cplan.sums.data(), R->cplan.sums.size() * sizeof(CorrSum),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(R->ws + P.o_cmap, R->cplan.map.data(), R->cplan.map.size() * 4, hipMemcpyHostToDevice,
+                          s));
+  }
   HIPCHK(hipMemsetAsync(R->ws + P.o_pairs, 0, 16, s));
   if (P.ups_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_ups, 0, P.ups_bytes, s));
   if (P.corr_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_corr, 0, P.corr_bytes, s));
-  // slice partials: the slots of correction sums shared with a smaller mu are
-  // never written, so they must hold zeros for the slice reduction
-  if (P.corr_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_cpart, 0, P.corr_bytes * CORR_SLICES, s));
   if (P.acc3_bytes) HIPCHK(hipMemsetAsync(R->ws + P.o_acc3, 0, P.acc3_bytes, s));
   double e2[FPCF4_NBINS_SUPPORTED + 1];
   for (int b = 0; b <= P.nb; ++b) e2[b] = bins->edges[b] * bins->edges[b];
@@ -503,7 +520,8 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
     HIPCHK(launch_contract_pairs(pl, s));
     if (prof) HIPCHK(hipEventRecord(evs[3], s));
     CorrArgs ca{a.rec, a.xg, a.xw, ncent, P.nb, P.nmax, (int32_t)P.ldc, R->at<double>(P.o_corr),
-                R->at<double>(P.o_cpart)};
+                R->at<double>(P.o_cpart), R->at<CorrSum>(P.o_csums), R->at<int32_t>(P.o_cmap), P.csums,
+                P.cpair};
     if (P.precision == FPCF4_FP64) HIPCHK(launch_corrections<double>(ca, s));
     else HIPCHK(launch_corrections<float>(ca, s));
     if (prof) {

@@ -58,35 +58,4 @@ __host__ __device__ constexpr MuCorr mu_corr(int mu) {
   }
 }
 
-__host__ __device__ constexpr bool same_fac_c(const Fac& a, const Fac& b) {
-  return a.fam == b.fam && a.conj == b.conj && a.a == b.a && a.b == b.b && a.c == b.c;
-}
-// Several correlators share a correction sum: the same centre factor, the
-// same Table 1 block and the same remaining factor (e.g. mu = 2 and 3 for
-// Theta_1 = Theta_2).  corr_canon(mu, kind) is the smallest mu' with the
-// same sum for kind 0 (c12 x C), 1 (c13 x B), 2 (A x c23) or 3 (t).
-__host__ __device__ constexpr bool same_corr(int m1, int m2, int kind) {
-  const MuFactors f1 = mu_factors(m1), f2 = mu_factors(m2);
-  const MuCorr c1 = mu_corr(m1), c2 = mu_corr(m2);
-  if (f1.x != f2.x) return false;
-  if (kind == 0) return same_fac_c(c1.c12, c2.c12) && same_fac_c(f1.C, f2.C);
-  if (kind == 1) return same_fac_c(c1.c13, c2.c13) && same_fac_c(f1.B, f2.B);
-  if (kind == 2) return same_fac_c(c1.c23, c2.c23) && same_fac_c(f1.A, f2.A);
-  return c1.t == c2.t;
-}
-__host__ __device__ constexpr int corr_canon(int mu, int kind) {
-  for (int m = 0; m < mu; ++m)
-    if (same_corr(m, mu, kind)) return m;
-  return mu;
-}
-struct CorrCanon {
-  int c[9][4];
-};
-__host__ __device__ constexpr CorrCanon corr_canon_table() {
-  CorrCanon t{};
-  for (int mu = 0; mu < 9; ++mu)
-    for (int k = 0; k < 4; ++k) t.c[mu][k] = corr_canon(mu, k);
-  return t;
-}
-
 }  // namespace fpcf4

@@ -167,13 +167,37 @@ hipError_t reduced_build(const double* x, const double* y, const double* g1, con
 template <typename T>
 hipError_t launch_stage_a(int nmax, int order, const StageAArgs& a, hipStream_t s, int* nlaunch, hipEvent_t mid);
 
+// One distinct degenerate-term sum, a GEMM over centres
+//   S[b, b'] = sum_i x_i E_i(b) F_i(b')
+// with E a Table 1 block at the equal bins and F the remaining factor; the
+// triple term has F = 1 (one column).
+struct CorrSum {
+  int8_t x, triple, eflip, fconj;  // centre factor (X_*); triple term; conjugate E / F
+  int32_t eidx, fidx;              // record entries of E and F
+};
+// Every (mu, kind, order) of the correction buffer (kind 0: Theta_1 = Theta_2,
+// 1: Theta_1 = Theta_3, 2: Theta_2 = Theta_3, 3: all equal) is one of a few
+// hundred distinct sums: the three pair kinds are all x E(b) F(b'), and
+// correlators share blocks.  sums holds the pair sums first, then the
+// triple sums; map[mu][slot] (slot = kind 0 orders, kind 1 orders, kind 2
+// orders, kind 3) names the sum.
+struct CorrPlanHost {
+  std::vector<CorrSum> sums;
+  int npair = 0;
+  std::vector<int32_t> map;        // [9][2 (2nmax+1) + (4nmax+1) + 1]
+};
+CorrPlanHost make_corr_plan(int nmax);
 struct CorrArgs {
   const void* rec;
   const void* xg;
   const void* xw;
   int32_t ncent, nb, nmax, ldc;
   double* corr;             // correction sums, accumulated over tiles
-  double* part;             // [CORR_SLICES][corr_elems] per-slice partial sums
+  double* part;             // [CORR_SLICES][corr_elems] per-slice partial sums: the
+                            // distinct sums, [npair][nb][nb] then [ntriple][nb]
+  const CorrSum* sums;      // the distinct sums (device)
+  const int32_t* map;       // (mu, kind, order) -> sum (device)
+  int32_t nsums, npair;
 };
 constexpr int CORR_SLICES = 8;   // centre slices of the correction sums
 

@@ -8,6 +8,17 @@
 //   P3[b]           nb         : sum_i x t(i,b)
 // Records are centre-contiguous, so a chunk of centres of one bin row is a
 // coalesced load.
+//
+// All three pair kinds are sums x E(b) F(b') with E the Table 1 block at the
+// equal bins and F the remaining factor at the other bin (P23 stores it as
+// [b'][b]), and correlators share blocks: at nmax = 10 the 9 x 84 sums of the
+// buffer are 292 distinct GEMMs plus the triple terms.  make_corr_plan lists
+// them; corr_kernel forms each once per centre slice, and
+// corr_scatter_kernel adds the slices of every buffer entry's sum in order.
+#include <algorithm>
+#include <array>
+#include <map>
+
 #include "factors.hpp"
 #include "fpcf4_internal.hpp"
 
@@ -25,49 +36,91 @@ static __host__ __device__ inline int64_t corr_mu_elems(int nb, int n) {
 }
 size_t corr_elems(int nb, int nmax) { return (size_t)(9 * corr_mu_elems(nb, nmax)); }
 
+// (mu, slot) with slot = kind 0 orders n3, kind 1 orders n2, kind 2 orders
+// s = n2 + n3, kind 3: the kind and its order
+static __host__ __device__ inline void corr_slot(int slot, int n, int& kind, int& ord) {
+  const int nn = 2 * n + 1, ns = 4 * n + 1;
+  ord = 0;
+  if (slot < nn) { kind = 0; ord = slot - n; }
+  else if ((slot -= nn) < nn) { kind = 1; ord = slot - n; }
+  else if ((slot -= nn) < ns) { kind = 2; ord = slot - 2 * n; }
+  else kind = 3;
+}
+
+CorrPlanHost make_corr_plan(int n) {
+  const Layout L = make_layout(n);
+  const int nn = 2 * n + 1, ns = 4 * n + 1, per_mu = 2 * nn + ns + 1;
+  CorrPlanHost P;
+  P.map.assign((size_t)9 * per_mu, -1);
+  std::map<std::array<int, 5>, int> pair_id;
+  std::map<std::array<int, 2>, int> triple_id;
+  std::vector<CorrSum> pairs, triples;
+  std::vector<std::pair<size_t, int>> triple_slots;
+  for (int mu = 0; mu < FPCF4_NCORR; ++mu) {
+    const MuFactors F = mu_factors(mu);
+    const MuCorr C = mu_corr(mu);
+    for (int slot = 0; slot < per_mu; ++slot) {
+      int kind, ord;
+      corr_slot(slot, n, kind, ord);
+      const size_t m = (size_t)mu * per_mu + slot;
+      if (kind == 3) {
+        const int e = L.offS + C.t;
+        const auto r = triple_id.emplace(std::array<int, 2>{F.x, e}, (int)triples.size());
+        if (r.second) triples.push_back(CorrSum{(int8_t)F.x, 1, 0, 0, e, e});
+        triple_slots.push_back({m, r.first->second});
+        continue;
+      }
+      // Table 1 block at the equal bins and the remaining factor, at this order
+      const Fac ce = kind == 0 ? C.c12 : (kind == 1 ? C.c13 : C.c23);
+      const int ke = kind == 0 ? ce.b * ord + ce.c : ce.a * ord + ce.c;
+      const Fac fo = kind == 0 ? F.C : (kind == 1 ? F.B : F.A);
+      const int ko = kind == 0 ? fo.b * ord + fo.c : fo.a * ord + fo.c;
+      int eidx, eflip = 0;
+      if (ce.fam == C_Q) {
+        eidx = eQ(L, ke);
+      } else {   // A and V are sums of real weights: X_-k = conj X_k
+        const int k = ke < 0 ? -ke : ke;
+        eidx = ce.fam == C_A ? eA(L, k) : eV(L, k);
+        eflip = ke < 0;
+      }
+      const int fidx = fo.fam == F_G ? eG(L, ko) : eW(L, ko);
+      const std::array<int, 5> key{F.x, eidx, eflip, fidx, fo.conj};
+      const auto r = pair_id.emplace(key, (int)pairs.size());
+      if (r.second) pairs.push_back(CorrSum{(int8_t)F.x, 0, (int8_t)eflip, (int8_t)fo.conj, eidx, fidx});
+      P.map[m] = r.first->second;
+    }
+  }
+  P.npair = (int)pairs.size();
+  for (const auto& ts : triple_slots) P.map[ts.first] = P.npair + ts.second;
+  P.sums = pairs;
+  P.sums.insert(P.sums.end(), triples.begin(), triples.end());
+  return P;
+}
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int CKC = 32;   // centres per LDS chunk
 
-// Each (mu, kind, order) is a small GEMM over the tile's centres,
+// Each distinct sum is a small GEMM over the tile's centres,
 //   P[b_eq, b'] = sum_c E[c, b_eq] F[c, b'],  E = x (Table 1 block), F = other factor,
 // done on v_mfma_f64_16x16x4_f64 with the complex product split into real
 // rows [[E_r, -E_i], [E_i, E_r]] and columns [F_r; F_i].  The triple term
 // (kind 3) is the same GEMM with F = 1 in column 0.  The four waves take
 // alternate K-steps of each LDS-staged chunk and are summed at the end.  The
 // centres are cut into CORR_SLICES contiguous slices (blockIdx.y), each
-// written to its own binary64 partial buffer; corr_reduce_kernel adds the
+// written to its own binary64 partial buffer; corr_scatter_kernel adds the
 // slices in a fixed order, so the sums stay deterministic.
 template <typename T>
 __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
-  const int nb = a.nb, n = a.nmax, nn = 2 * n + 1, ns = 4 * n + 1;
-  const Layout L = make_layout(n);
-  const int per_mu = 2 * nn + ns + 1;
-  const int lb = (int)blockIdx.x;
-  const int mu = lb / per_mu;
-  int r = lb % per_mu;
-  int kind, ord = 0;
-  if (r < nn) { kind = 0; ord = r - n; }
-  else if ((r -= nn) < nn) { kind = 1; ord = r - n; }
-  else if ((r -= nn) < ns) { kind = 2; ord = r - 2 * n; }
-  else { kind = 3; }
-  // a sum shared with a smaller mu is formed there only (the finalisation
-  // reads it from that mu); this workgroup has nothing to do
-  if (corr_canon(mu, kind) != mu) return;
+  const int nb = a.nb;
+  const int sidx = (int)blockIdx.x;
+  const CorrSum cs = a.sums[sidx];
+  const int kind = cs.triple ? 3 : 0;   // 3: F = 1 in column 0
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const MuFactors F = mu_factors(mu);
-  const MuCorr C = mu_corr(mu);
   const T* xg = reinterpret_cast<const T*>(a.xg);
   const T* xw = reinterpret_cast<const T*>(a.xw);
-  // equal-bin block (Table 1) and the remaining factor, selected by value
-  const Fac ce = kind == 0 ? C.c12 : (kind == 1 ? C.c13 : C.c23);
-  const int ke = kind == 0 ? ce.b * ord + ce.c : ce.a * ord + ce.c;
-  const Fac fo = kind == 0 ? F.C : (kind == 1 ? F.B : F.A);
-  const int ko = kind == 0 ? fo.b * ord + fo.c : fo.a * ord + fo.c;
-  const int e_fo = fo.fam == F_G ? eG(L, ko) : eW(L, ko);
-  const bool fo_conj = fo.conj != 0;
-  const int ce_fam = ce.fam;
-  const int t_entry = L.offS + C.t;
-  const int xkind = F.x;
+  const int e_fo = cs.fidx;
+  const bool fo_conj = cs.fconj != 0;
+  const int xkind = cs.x;
   const int ncent = a.ncent;
   const int nch_all = (ncent + CKC - 1) / CKC;
   const int ch0 = (int)(((int64_t)nch_all * blockIdx.y) / gridDim.y);
@@ -86,18 +139,8 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
 
   // Row pointers and conjugations of this thread's two (bin, centre) slots,
   // resolved once: per chunk a slot is three plain loads at centre c.
-  int eidx, eflip;   // Table 1 block entry; conjugate (A, V at negative order)
-  if (kind == 3) {
-    eidx = t_entry;
-    eflip = 0;
-  } else if (ce_fam == C_Q) {
-    eidx = eQ(L, ke);
-    eflip = 0;
-  } else {
-    const int k = ke < 0 ? -ke : ke;
-    eidx = ce_fam == C_A ? eA(L, k) : eV(L, k);
-    eflip = ke < 0;
-  }
+  const int eidx = cs.eidx;      // Table 1 block entry
+  const int eflip = cs.eflip;    // conjugate (A, V at negative order)
   const T* rec = reinterpret_cast<const T*>(a.rec);
   const T* pe_row[2];
   const T* pf_row[2];
@@ -208,7 +251,8 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
   red[wv][1][lane] = acc[1];
   __syncthreads();
   if (wv != 0) return;
-  double* out = a.part + 2 * ((int64_t)(9 * blockIdx.y + mu) * corr_mu_elems(nb, n));
+  // this slice's region: pair sums [npair][nb][nb], then triple sums [nb]
+  double* out = a.part + 2 * ((int64_t)blockIdx.y * 9 * corr_mu_elems(nb, a.nmax));
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
     const d4 v = red[0][m][lane] + red[1][m][lane] + red[2][m][lane] + red[3][m][lane];
@@ -217,36 +261,62 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrArgs a) {
       const int row = 16 * m + 4 * e + (lane >> 4);   // f64 D layout
       if (row >= 2 * ne || !cok || (kind == 3 && col != 0)) continue;
       const int part = row / ne, beq = oe + row % ne, bo = of + col;
-      int64_t o;
-      if (kind == 0) o = ((int64_t)beq * nb + bo) * nn + (ord + n);
-      else if (kind == 1) o = (int64_t)nb * nb * nn + ((int64_t)beq * nb + bo) * nn + (ord + n);
-      else if (kind == 2) o = 2LL * nb * nb * nn + ((int64_t)bo * nb + beq) * ns + (ord + 2 * n);
-      else o = 2LL * nb * nb * nn + (int64_t)nb * nb * ns + beq;
+      const int64_t o = kind == 3 ? (int64_t)a.npair * nb * nb + (int64_t)(sidx - a.npair) * nb + beq
+                                  : ((int64_t)sidx * nb + beq) * nb + bo;
       out[2 * o + part] = v[e];
     }
   }
 }
 
-// corr += sum over slices of the partial sums, slice by slice
-__global__ void corr_reduce_kernel(const double* part, int64_t elems, double* corr) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= elems) return;
-  double v = corr[i];
+// corr += sum over slices of the distinct sum each entry of the buffer reads,
+// slice by slice (deterministic)
+__global__ void corr_scatter_kernel(const double* part, const int32_t* map, int npair, int nb, int n,
+                                    double* corr) {
+  const int nn = 2 * n + 1, ns = 4 * n + 1, per_mu = 2 * nn + ns + 1;
+  const int64_t mu_elems = corr_mu_elems(nb, n), slice = 2 * 9 * mu_elems;
+  const int64_t total = 2 * 9 * mu_elems;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(i & 1);
+    const int64_t o = i >> 1;
+    const int mu = (int)(o / mu_elems);
+    int64_t r = o % mu_elems;
+    int slot, beq, bo = 0;
+    const int64_t pq = (int64_t)nb * nb * nn;
+    if (r < 2 * pq) {                        // P12 [b][b3][n3], P13 [b][b2][n2]
+      const int k = (int)(r / pq);
+      r %= pq;
+      slot = k * nn + (int)(r % nn);
+      bo = (int)((r / nn) % nb);
+      beq = (int)(r / nn / nb);
+    } else if ((r -= 2 * pq) < (int64_t)nb * nb * ns) {   // P23 [b1][b][s]
+      slot = 2 * nn + (int)(r % ns);
+      beq = (int)((r / ns) % nb);
+      bo = (int)(r / ns / nb);
+    } else {                                 // P3 [b]
+      slot = 2 * nn + ns;
+      beq = (int)(r - (int64_t)nb * nb * ns);
+    }
+    const int sum = map[mu * per_mu + slot];
+    const int64_t src = sum < npair ? ((int64_t)sum * nb + beq) * nb + bo
+                                    : (int64_t)npair * nb * nb + (int64_t)(sum - npair) * nb + beq;
+    double v = corr[i];
 #pragma unroll
-  for (int sl = 0; sl < CORR_SLICES; ++sl) v += part[sl * elems + i];
-  corr[i] = v;
+    for (int sl = 0; sl < CORR_SLICES; ++sl) v += part[sl * slice + 2 * src + p];
+    corr[i] = v;
+  }
 }
 
 template <typename T>
 hipError_t launch_corrections(const CorrArgs& a, hipStream_t s) {
   if (a.ncent <= 0) return hipSuccess;
-  const int nn = 2 * a.nmax + 1, ns = 4 * a.nmax + 1;
-  const int blocks = 9 * (2 * nn + ns + 1);
+  if (a.nsums <= 0 || a.npair < 0 || a.npair > a.nsums) return hipErrorInvalidValue;
   const BinTiles bt = bin_tiles(a.nb);
-  hipLaunchKernelGGL(corr_kernel<T>, dim3(blocks, CORR_SLICES, bt.nt * bt.nt), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(corr_kernel<T>, dim3(a.nsums, CORR_SLICES, bt.nt * bt.nt), dim3(256), 0, s, a);
   const int64_t elems = 2 * (int64_t)corr_elems(a.nb, a.nmax);
-  hipLaunchKernelGGL(corr_reduce_kernel, dim3((int)((elems + 255) / 256)), dim3(256), 0, s,
-                     (const double*)a.part, elems, a.corr);
+  const int64_t blocks = std::min<int64_t>((elems + 255) / 256, 1 << 16);
+  hipLaunchKernelGGL(corr_scatter_kernel, dim3((int)blocks), dim3(256), 0, s, (const double*)a.part, a.map,
+                     a.npair, a.nb, a.nmax, a.corr);
   return hipGetLastError();
 }
 template hipError_t launch_corrections<double>(const CorrArgs&, hipStream_t);
@@ -268,9 +338,8 @@ __global__ void finalize_kernel(const double* raw, const double* corr, int nb, i
       const int b2 = (int)(t % nb); t /= nb;
       const int b1 = (int)(t % nb); t /= nb;
       const int mu = (int)t;
-      constexpr CorrCanon canon = corr_canon_table();
-      // each kind's sum lives at the smallest mu that shares it
-      auto Ck = [&](int kind) { return corr + 2 * (int64_t)canon.c[mu][kind] * corr_mu_elems(nb, n); };
+      // every kind of every mu holds its sums (filled from the distinct ones)
+      auto Ck = [&](int) { return corr + 2 * (int64_t)mu * corr_mu_elems(nb, n); };
       if (b1 == b2) {
         const double* C = Ck(0);
         const int64_t q = ((int64_t)b1 * nb + b3) * nn + (n3 + n);
