@@ -529,7 +529,9 @@ fpcf4_status request_step(fpcf4_request* R, int64_t tile, bool stage_b) {
       R->prof_b_flops += pair_issued_flops(R->pplan, P.nb, ncent, P.precision);
       R->prof_b_useful += pair_useful_flops(R->pplan, P.nb, ncent);
       R->prof_a_launches += nlaunch;
-      R->prof_b_launches += R->pplan.cls_count[1] > 0 && R->pplan.cls_count[2] > 0 ? 3 : 2;
+      // one kernel per row-block class, the slice sum (several slices), the scatter
+      R->prof_b_launches += (R->pplan.cls_count[1] > 0) + (R->pplan.cls_count[2] > 0) +
+                            (std::min(pair_slices(ncent), P.pslices) > 1) + 1;
       R->prof_steps += 1;
       R->prof_centres += ncent;
     }

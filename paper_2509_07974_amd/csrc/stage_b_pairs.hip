@@ -41,9 +41,10 @@
 // an fp32 running sum over at most 8192 centres, which is converted to
 // binary64 (unscaled exactly) and written into the workgroup's own region of
 // the slice partial buffer (the first sub-slice stores, later ones add: the
-// same lanes read back what they wrote).  pair_reduce_kernel adds the slices
-// in order and scatters every (mu, n2, n3) from its item and permutation
-// into the output tensor.  No atomics: the result is deterministic.
+// same lanes read back what they wrote).  pair_slice_sum_kernel adds the
+// slices in order (coalesced, into the first slice) and pair_reduce_kernel
+// scatters every (mu, n2, n3) from its item and permutation into the output
+// tensor.  No atomics: the result is deterministic.
 #include <algorithm>
 #include <array>
 #include <map>
@@ -828,6 +829,17 @@ __global__ __launch_bounds__(64 * pair_waves(NBLK, NBC)) void contract_pair_f64_
   }
 }
 
+// part[0][e] = sum over the slices of part[k][e], in slice order (the
+// contraction rewrites every slice it reads next time)
+__global__ void pair_slice_sum_kernel(double* part, int nsl, int64_t slice_elems) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < slice_elems;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int k = 0; k < nsl; ++k) v += part[(int64_t)k * slice_elems + e];
+    part[e] = v;
+  }
+}
+
 // ups[mu][b1][b2][b3][n2][n3] += sum over slices of the item region that holds
 // (mu, n2, n3), read at (b1, b2, b3) permuted into the item's roles
 __global__ void pair_reduce_kernel(const double* part, int nsl, int64_t slice_elems, const PairItem* items,
@@ -942,10 +954,16 @@ hipError_t launch_contract_pairs(const PairLaunch& pl, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   const int nn = 2 * pl.nmax + 1;
+  const int64_t slice_elems = pl.total_rows * pl.nb * pl.nb;
+  if (nsl > 1) {
+    const int64_t sblocks = std::min<int64_t>((slice_elems + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(pair_slice_sum_kernel, dim3((unsigned)sblocks), dim3(256), 0, s, pl.part, nsl,
+                       slice_elems);
+  }
   const int64_t total = 2LL * FPCF4_NCORR * pl.nb * pl.nb * pl.nb * nn * nn;
   const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1 << 16);
-  hipLaunchKernelGGL(pair_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pl.part, nsl,
-                     pl.total_rows * pl.nb * pl.nb, pl.items, pl.out, pl.nb, pl.nmax, pl.ups);
+  hipLaunchKernelGGL(pair_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pl.part, 1, slice_elems,
+                     pl.items, pl.out, pl.nb, pl.nmax, pl.ups);
   return hipGetLastError();
 }
 
