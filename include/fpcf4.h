@@ -262,6 +262,23 @@ fpcf4_status fpcf4_debug_multipoles(const fpcf4_catalogue *cat,
  * FPCF4_E_INVALID_ARG for nmax outside [0, FPCF4_NMAX_SUPPORTED] or a null out. */
 fpcf4_status fpcf4_debug_pair_plan(int32_t nmax, int32_t *out, int64_t *nitems);
 
+/* The degenerate-term sums of the subtraction (App. A.1, Table 1), for checks
+ * (host only: no device work).  Every entry of the correction buffer is
+ * sum_i x_i E_i(b) F_i(b'): E the Table 1 block at the equal bins, F the
+ * remaining factor at the other bin (F = 1 for the triple term); the
+ * library forms each distinct (x, E, F) once.  For every mu and slot (the
+ * 2nmax+1 orders n3 of Theta_1 = Theta_2, the 2nmax+1 orders n2 of
+ * Theta_1 = Theta_3, the 4nmax+1 orders n2 + n3 of Theta_2 = Theta_3, then
+ * the triple term), writes 8 int32 to out (host memory,
+ * 9 (8 nmax + 4) * 8 values):
+ *   [0] centre factor: 0 = w gamma, 1 = its conjugate, 2 = w
+ *   [1] E family: 2 = Q, 3 = A, 4 = V, 5 = T, 6 = M, 7 = U;  [2] E order
+ *   [3] F family: 0 = G, 1 = W, -1 for the triple term; [4] F conjugated;
+ *   [5] F order;  [6] the distinct sum;  [7] 0
+ * *nsums (may be NULL) receives the number of distinct sums.
+ * FPCF4_E_INVALID_ARG for nmax outside [0, FPCF4_NMAX_SUPPORTED] or a null out. */
+fpcf4_status fpcf4_debug_corr_plan(int32_t nmax, int32_t *out, int64_t *nsums);
+
 /* Conversion to bin-averaged natural components (Sect. 2.3 and Eq. of the
  * multipole expansion in Sect. 3.1): for nphi linear angular bins on
  * [0, 2pi),

@@ -17,7 +17,7 @@ from ._lib import (FP64, MIXED_FP16, MIXED_BF16, MEM_HOST, MEM_DEVICE, NMAX_SUPP
                    NBINS_SUPPORTED, Fpcf4Error, check, lib)
 
 __all__ = ["estimate_4pcf_multipoles", "estimate_4pcf_multipoles_noalloc", "estimate_3pcf_multipoles",
-           "debug_multipoles", "debug_pair_plan", "to_natural",
+           "debug_multipoles", "debug_pair_plan", "debug_corr_plan", "to_natural",
            "to_natural_triplets", "natural_blocks", "plan", "Request",
            "profile_enable", "profile_read",
            "PRECISIONS", "Fpcf4Error", "output_shape", "output3_shape", "lib", "version",
@@ -303,6 +303,16 @@ def debug_pair_plan(nmax: int):
     nit = C.c_int64(0)
     check(lib().fpcf4_debug_pair_plan(int(nmax), out.ctypes.data, C.byref(nit)))
     return out, int(nit.value)
+
+
+def debug_corr_plan(nmax: int):
+    """The distinct degenerate-term sums (host only): an int32 array
+    [9, 8 nmax + 4, 8] as fpcf4_debug_corr_plan documents it, and the number
+    of distinct sums."""
+    out = np.zeros((9, 8 * nmax + 4, 8), dtype=np.int32)
+    ns = C.c_int64(0)
+    check(lib().fpcf4_debug_corr_plan(int(nmax), out.ctypes.data, C.byref(ns)))
+    return out, int(ns.value)
 
 
 def profile_enable(on: bool = True):

@@ -1056,6 +1056,50 @@ fpcf4_status fpcf4_debug_pair_plan(int32_t nmax, int32_t* out, int64_t* nitems) 
   return FPCF4_OK;
 }
 
+fpcf4_status fpcf4_debug_corr_plan(int32_t nmax, int32_t* out, int64_t* nsums) {
+  if (nmax < 0 || nmax > FPCF4_NMAX_SUPPORTED) return fail(FPCF4_E_INVALID_ARG, "nmax %d outside [0, %d]", nmax,
+                                                          FPCF4_NMAX_SUPPORTED);
+  if (!out) return fail(FPCF4_E_INVALID_ARG, "null out");
+  const CorrPlanHost cp = make_corr_plan(nmax);
+  const Layout L = make_layout(nmax);
+  // record entry -> (family code, signed order) of the block it holds
+  auto block_of = [&](int e, int flip, int& fam, int& ord) {
+    if (e >= L.offS) {   // triple blocks T_-8, T_-4, M_-4, M_0, U
+      static const int tf[5] = {5, 5, 6, 6, 7}, to[5] = {-8, -4, -4, 0, 0};
+      fam = tf[e - L.offS];
+      ord = to[e - L.offS];
+    } else if (e >= L.offV) {
+      fam = 4;
+      ord = flip ? -(e - L.offV) : e - L.offV;
+    } else if (e >= L.offA) {
+      fam = 3;
+      ord = flip ? -(e - L.offA) : e - L.offA;
+    } else if (e >= L.offQ) {
+      fam = 2;
+      ord = e - L.offQ + L.qlo;
+    } else if (e >= L.offW) {
+      fam = 1;   // W
+      ord = e - L.offW - 2 * nmax;
+    } else {
+      fam = 0;   // G
+      ord = e - L.offG - (2 * nmax + 3);
+    }
+  };
+  for (size_t m = 0; m < cp.map.size(); ++m) {
+    const int sidx = cp.map[m];
+    if (sidx < 0 || sidx >= (int)cp.sums.size())
+      return fail(FPCF4_E_DEVICE, "internal: correction plan leaves a sum unassigned");
+    const CorrSum& c = cp.sums[sidx];
+    int ef, eo, ff = -1, fo = 0;
+    block_of(c.eidx, c.eflip, ef, eo);
+    if (!c.triple) block_of(c.fidx, 0, ff, fo);
+    const int32_t vals[8] = {c.x, ef, eo, ff, c.triple ? 0 : c.fconj, fo, sidx, 0};
+    for (int k = 0; k < 8; ++k) out[8 * m + k] = vals[k];
+  }
+  if (nsums) *nsums = (int64_t)cp.sums.size();
+  return FPCF4_OK;
+}
+
 fpcf4_status fpcf4_debug_multipoles(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
                                     const fpcf4_options* opts_in, int64_t* counts, double* G, double* W) {
   if (!cat || !bins || !opts_in) return fail(FPCF4_E_INVALID_ARG, "null argument");

@@ -75,3 +75,63 @@ def test_plan_rejects_bad_arguments(lib):
     assert lib.fpcf4_debug_pair_plan(0, None, None) != 0
     n = C.c_int64(0)
     assert lib.fpcf4_debug_pair_plan(0, out.ctypes.data, C.byref(n)) == 0 and n.value > 0
+
+
+# ---------------------------------------------------------------------------
+# degenerate-term sums (App. A.1, Table 1)
+# ---------------------------------------------------------------------------
+E_FAMILY = {"Q": 2, "A": 3, "V": 4, "T": 5, "M": 6, "U": 7}
+
+
+def corr_terms(mu, nmax):
+    """Per slot of the correction buffer (orders n3 of Theta_1 = Theta_2,
+    orders n2 of Theta_1 = Theta_3, orders n2 + n3 of Theta_2 = Theta_3, the
+    triple term): x, the Table 1 block (family, order) and the remaining
+    factor (family, conjugated, order), from the oracle's tables."""
+    x, A, B, C = est.FACTORS[mu]
+    c12, c13, c23, t = est.TABLE1[mu]
+    out = []
+    for kind, (eb, fb, orders) in enumerate(((c12, C, range(-nmax, nmax + 1)),
+                                            (c13, B, range(-nmax, nmax + 1)),
+                                            (c23, A, range(-2 * nmax, 2 * nmax + 1)))):
+        for o in orders:
+            # the sum's order index: n3 (kind 0), n2 (kind 1), s = n2 + n3 (kind 2)
+            n2, n3 = {0: (0, o), 1: (o, 0), 2: (o, 0)}[kind]
+            ea, ebb, ec = eb[1]
+            fa, fbb, fc = fb[2]
+            if kind == 2:   # both orders depend on s = n2 + n3 only (a = b)
+                assert ea == ebb and fa == fbb
+            e = (E_FAMILY[eb[0]], ea * n2 + ebb * n3 + ec)
+            f = (FAMILY[fb[0]], int(fb[1]), fa * n2 + fbb * n3 + fc)
+            out.append((X_KIND[x], e, f))
+    out.append((X_KIND[x], (E_FAMILY[t[0]], t[1][2]), None))
+    return out
+
+
+@pytest.mark.parametrize("nmax", [0, 1, 3, 8, 10, 15, 16])
+def test_corr_plan_forms_each_table1_sum_once(lib, nmax):
+    import paper_2509_07974_amd as fp
+    plan, nsums = fp.debug_corr_plan(nmax)
+    assert plan.shape == (9, 8 * nmax + 4, 8)
+    key_of_sum = {}
+    keys = set()
+    for mu in range(9):
+        terms = corr_terms(mu, nmax)
+        assert len(terms) == plan.shape[1]
+        for slot, (x, e, f) in enumerate(terms):
+            v = [int(t) for t in plan[mu, slot]]
+            assert v[0] == x, (mu, slot)
+            assert (v[1], v[2]) == e, (mu, slot, v, e)
+            if f is None:
+                assert v[3] == -1
+            else:
+                assert (v[3], v[4], v[5]) == f, (mu, slot, v, f)
+            key = (x, e, f)
+            keys.add(key)
+            # one distinct sum per (x, E, F), and no two keys share a sum
+            assert key_of_sum.setdefault(v[6], key) == key
+            assert 0 <= v[6] < nsums
+    assert len(key_of_sum) == len(keys) == nsums
+    # the three pair kinds share sums: fewer than the 9 (8 nmax + 3) pair slots
+    if nmax >= 1:
+        assert nsums < 9 * (8 * nmax + 4)
