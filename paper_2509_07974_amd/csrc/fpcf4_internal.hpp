@@ -203,19 +203,22 @@ constexpr int CORR_SLICES = 8;   // centre slices of the correction sums
 
 template <typename T> hipError_t launch_corrections(const CorrArgs& a, hipStream_t s);
 
-// Contraction on the matrix cores, organised by the pair of blocks at
-// Theta_2 and Theta_3 (stage_b_pairs.hip; every precision).  A work item is one unordered pair of
-// (family, conjugation, order) for the b2 and b3 factors; its row blocks are
-// the distinct left factors x A(b1) of every (mu, n2, n3) using that pair.
+// Contraction on the matrix cores (stage_b_pairs.hip; every precision).
+// Each distinct product x D E F of three blocks (with the centre factor x)
+// is formed once over all bin triples: a work item is an unordered pair of
+// column blocks (E, F), each (family, conjugation, order), whose Khatri-Rao
+// product is formed once; its row blocks are the third blocks x D of the
+// products assigned to that pair.  Every (mu, n2, n3) reads its product at
+// its bins permuted into the item's roles.
 constexpr int PAIR_MAX_BLK = 2;    // row blocks per work item (pairs with more are split)
 constexpr int PAIR_SUB = 8192;     // centres per binary32 running sum before binary64
 struct PairRow {
-  int8_t x, fam, conj, pad;        // centre factor kind (X_*), A family (F_*), A conjugated
-  int32_t order;                   // A order
+  int8_t x, fam, conj, pad;        // centre factor kind (X_*), row block family (F_*), conjugated
+  int32_t order;                   // row block order
 };
 struct PairItem {
-  int8_t famB, conjB, famC, conjC;
-  int32_t ordB, ordC;
+  int8_t famB, conjB, famC, conjC; // first and second column block: family, conjugated
+  int32_t ordB, ordC;              // their orders
   int32_t nblk;                    // row blocks
   int32_t row0;                    // first row of the item in the partial layout
   int32_t pad;
