@@ -58,7 +58,7 @@ inline size_t up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
 constexpr size_t kTileRecordBudget = size_t(32) << 30;
 // Centre slices of the pair contraction each own a binary64 partial of all
 // work items; their number is cut so the partials stay below this many bytes
-// (one slice at least: at 65 bins and nmax 15 one slice is about 21 GB).
+// (one slice at least: at 65 bins and nmax 15 one slice is about 10 GB).
 constexpr size_t kPairPartialBudget = size_t(48) << 30;
 // Scheduling counters of stage (a) (8 per launch, two launches), then the
 // per-bin scaling maxima.
@@ -79,7 +79,7 @@ struct PlanInfo {
   size_t o_gal, o_cells, o_centres, o_e2, o_edges, o_counters, o_bbox, o_bad,
       o_pairs, o_part, o_ups, o_corr, o_cpart, o_acc3, o_part3, o_xg, o_xw, o_counts,
       o_aos, o_region, o_pitems, o_pout, o_ppart, o_csums, o_cmap;
-  // mixed-precision contraction by Theta_2/Theta_3 block pairs
+  // contraction work items (each distinct product of three blocks once)
   int pslices = 0;
   int64_t pitems = 0, prows = 0;
   // distinct degenerate-term sums
@@ -280,7 +280,7 @@ struct fpcf4_request {
   char* ws = nullptr;
   Grid grid{};
   std::vector<char> stepped;
-  PairPlanHost pplan;           // the pair plan uploaded into the workspace (mixed 4PCF)
+  PairPlanHost pplan;           // the contraction plan uploaded into the workspace (4PCF)
   CorrPlanHost cplan;           // the distinct degenerate-term sums, likewise
   bool want_counts = false;
   bool no_events = false;       // allocation-free path: never create profiling events
