@@ -199,7 +199,7 @@ struct CorrArgs {
   const int32_t* map;       // (mu, kind, order) -> sum (device)
   int32_t nsums, npair;
 };
-constexpr int CORR_SLICES = 8;   // centre slices of the correction sums
+constexpr int CORR_SLICES = 13;  // centre slices of the correction sums
 
 template <typename T> hipError_t launch_corrections(const CorrArgs& a, hipStream_t s);
 
