@@ -279,6 +279,20 @@ fpcf4_status fpcf4_debug_pair_plan(int32_t nmax, int32_t *out, int64_t *nitems);
  * FPCF4_E_INVALID_ARG for nmax outside [0, FPCF4_NMAX_SUPPORTED] or a null out. */
 fpcf4_status fpcf4_debug_corr_plan(int32_t nmax, int32_t *out, int64_t *nsums);
 
+/* The stable radix sort of the cell-list build, for checks (the spatial sort
+ * that puts the neighbours of the pair sums of Sect. 3.1 / App. A cell by
+ * cell, and the cells of the reduced catalogues of Sect. 3.2).  Sorts the n
+ * (key, value) pairs by key, equal keys keeping their input order, on the
+ * device (key_bytes 4: 32-bit keys, as the cell and Morton keys; 8: 64-bit,
+ * as the reduced-catalogue cells).  keys, vals (inputs) and keys_out,
+ * vals_out (outputs) are host arrays of n entries; keys are passed as
+ * uint64 in both cases.  FPCF4_E_INVALID_ARG for n outside [0, 2^31),
+ * key_bytes not 4 or 8, key_bits outside [1, 8 key_bytes], a key not below
+ * 2^key_bits or a null array with n > 0; FPCF4_E_DEVICE on a device error. */
+fpcf4_status fpcf4_debug_sort_pairs(const uint64_t *keys, const int32_t *vals, int64_t n,
+                                    int32_t key_bits, int32_t key_bytes, uint64_t *keys_out,
+                                    int32_t *vals_out);
+
 /* Conversion to bin-averaged natural components (Sect. 2.3 and Eq. of the
  * multipole expansion in Sect. 3.1): for nphi linear angular bins on
  * [0, 2pi),

@@ -17,7 +17,7 @@ from ._lib import (FP64, MIXED_FP16, MIXED_BF16, MEM_HOST, MEM_DEVICE, NMAX_SUPP
                    NBINS_SUPPORTED, Fpcf4Error, check, lib)
 
 __all__ = ["estimate_4pcf_multipoles", "estimate_4pcf_multipoles_noalloc", "estimate_3pcf_multipoles",
-           "debug_multipoles", "debug_pair_plan", "debug_corr_plan", "to_natural",
+           "debug_multipoles", "debug_pair_plan", "debug_corr_plan", "debug_sort_pairs", "to_natural",
            "to_natural_triplets", "natural_blocks", "plan", "Request",
            "profile_enable", "profile_read",
            "PRECISIONS", "Fpcf4Error", "output_shape", "output3_shape", "lib", "version",
@@ -313,6 +313,21 @@ def debug_corr_plan(nmax: int):
     ns = C.c_int64(0)
     check(lib().fpcf4_debug_corr_plan(int(nmax), out.ctypes.data, C.byref(ns)))
     return out, int(ns.value)
+
+
+def debug_sort_pairs(keys, vals, key_bits: int, key_bytes: int = 8):
+    """The cell-list build's stable radix sort on the device (host arrays in
+    and out): keys (uint64, each below 2^key_bits) and int32 vals sorted by
+    key, equal keys in input order; key_bytes 4 runs the 32-bit-key sort."""
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    v = np.ascontiguousarray(vals, dtype=np.int32)
+    if k.ndim != 1 or v.shape != k.shape:
+        raise ValueError("keys and vals must be 1-D arrays of one length")
+    ko = np.empty_like(k)
+    vo = np.empty_like(v)
+    check(lib().fpcf4_debug_sort_pairs(k.ctypes.data, v.ctypes.data, k.size, int(key_bits), int(key_bytes),
+                                       ko.ctypes.data, vo.ctypes.data))
+    return ko, vo
 
 
 def profile_enable(on: bool = True):

@@ -85,6 +85,9 @@ def lib():
     L.fpcf4_debug_pair_plan.restype = C.c_int32
     L.fpcf4_debug_corr_plan.argtypes = [C.c_int32, C.c_void_p, P(C.c_int64)]
     L.fpcf4_debug_corr_plan.restype = C.c_int32
+    L.fpcf4_debug_sort_pairs.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p,
+                                         C.c_void_p]
+    L.fpcf4_debug_sort_pairs.restype = C.c_int32
     L.fpcf4_to_natural.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     L.fpcf4_to_natural.restype = C.c_int32
     L.fpcf4_plan.argtypes = [P(Catalogue), P(Bins), P(Options), P(C.c_size_t), P(C.c_int64)]
@@ -139,4 +142,5 @@ EXPORTED = [
     "fpcf4_profile_enable", "fpcf4_profile_read", "estimate_3pcf_multipoles", "fpcf4_output3_elems",
     "fpcf4_to_natural_triplets", "estimate_4pcf_multipoles_tree", "estimate_4pcf_multipoles_noalloc",
     "estimate_3pcf_multipoles_doubletree", "fpcf4_debug_pair_plan", "fpcf4_debug_corr_plan",
+    "fpcf4_debug_sort_pairs",
 ]

@@ -52,7 +52,7 @@ def _jobs():
     hip = _hipcc()
     jobs = []
     for src in ("api.hip", "cells.hip", "stage_b.hip", "stage_b_pairs.hip", "natural.hip",
-                "threepcf.hip", "stage_a.hip"):
+                "threepcf.hip", "sort.hip", "stage_a.hip"):
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         jobs.append([hip, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
     for n in range(NMAX_SUPPORTED + 1):

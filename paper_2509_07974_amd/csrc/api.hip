@@ -1100,6 +1100,42 @@ fpcf4_status fpcf4_debug_corr_plan(int32_t nmax, int32_t* out, int64_t* nsums) {
   return FPCF4_OK;
 }
 
+fpcf4_status fpcf4_debug_sort_pairs(const uint64_t* keys, const int32_t* vals, int64_t n, int32_t key_bits,
+                                    int32_t key_bytes, uint64_t* keys_out, int32_t* vals_out) {
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(FPCF4_E_INVALID_ARG, "n %lld outside [0, 2^31)", (long long)n);
+  if (key_bytes != 4 && key_bytes != 8) return fail(FPCF4_E_INVALID_ARG, "key_bytes %d is not 4 or 8", key_bytes);
+  if (key_bits < 1 || key_bits > 8 * key_bytes)
+    return fail(FPCF4_E_INVALID_ARG, "key_bits %d outside [1, %d]", key_bits, 8 * key_bytes);
+  if (n == 0) return FPCF4_OK;
+  if (!keys || !vals || !keys_out || !vals_out) return fail(FPCF4_E_INVALID_ARG, "null argument");
+  for (int64_t i = 0; i < n; ++i)
+    if (key_bits < 64 && (keys[i] >> key_bits) != 0)
+      return fail(FPCF4_E_INVALID_ARG, "key %lld is not below 2^%d", (long long)i, key_bits);
+  const size_t kb = (size_t)n * key_bytes, vb = (size_t)n * 4, tb = radix_sort_temp_bytes(n);
+  auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+  char* d = nullptr;
+  HIPCHK(hipMalloc(&d, 2 * up(kb) + 2 * up(vb) + tb));
+  std::vector<uint32_t> k32(key_bytes == 4 ? n : 0);
+  for (size_t i = 0; i < k32.size(); ++i) k32[i] = (uint32_t)keys[i];
+  char *ka = d, *kbuf = d + up(kb), *va = d + 2 * up(kb), *vbuf = va + up(vb), *tmp = vbuf + up(vb);
+  hipError_t e = hipMemcpy(ka, key_bytes == 4 ? (const void*)k32.data() : (const void*)keys, kb, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(va, vals, vb, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = key_bytes == 4
+            ? radix_sort_pairs(tmp, tb, reinterpret_cast<uint32_t*>(ka), reinterpret_cast<uint32_t*>(kbuf),
+                               reinterpret_cast<int32_t*>(va), reinterpret_cast<int32_t*>(vbuf), n, key_bits, nullptr)
+            : radix_sort_pairs(tmp, tb, reinterpret_cast<uint64_t*>(ka), reinterpret_cast<uint64_t*>(kbuf),
+                               reinterpret_cast<int32_t*>(va), reinterpret_cast<int32_t*>(vbuf), n, key_bits, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(key_bytes == 4 ? (void*)k32.data() : (void*)keys_out, kbuf, kb, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(vals_out, vbuf, vb, hipMemcpyDeviceToHost);
+  const hipError_t ef = hipFree(d);
+  if (e == hipSuccess) e = ef;
+  if (e != hipSuccess) return fail(FPCF4_E_DEVICE, "sort: %s", hipGetErrorString(e));
+  for (size_t i = 0; i < k32.size(); ++i) keys_out[i] = k32[i];
+  return FPCF4_OK;
+}
+
 fpcf4_status fpcf4_debug_multipoles(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
                                     const fpcf4_options* opts_in, int64_t* counts, double* G, double* W) {
   if (!cat || !bins || !opts_in) return fail(FPCF4_E_INVALID_ARG, "null argument");

@@ -3,14 +3,12 @@
 //
 //  bbox_kernel    : min/max of x and y and a count of non-finite inputs
 //  key_kernel     : cell key cy * ncx + cx of every galaxy
-//  (hipcub radix sort of (key, index) pairs: stable, deterministic)
+//  (radix_sort_pairs of (key, index) pairs: stable, deterministic)
 //  starts_kernel  : cell_start[c] = first sorted position of cell c
 //  gather_kernel  : sorted galaxy records (x, y, w g1, w g2, w) and the
 //                   inverse permutation
 //  morton_kernel  : Morton key of each sorted galaxy's cell, so that the
 //                   centre list (sorted by it) visits space in compact blocks
-#include <hipcub/hipcub.hpp>
-
 #include <algorithm>
 
 #include "fpcf4_internal.hpp"
@@ -158,13 +156,7 @@ hipError_t cells_bbox(const double* x, const double* y, const double* g1, const 
   return hipGetLastError();
 }
 
-size_t cells_sort_temp_bytes(int64_t n) {
-  size_t b1 = 0, b2 = 0;
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b1, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                           (const int32_t*)nullptr, (int32_t*)nullptr, (int)n, 0, 32);
-  b2 = b1 + 4096;
-  return b1 > b2 ? b1 : b2;
-}
+size_t cells_sort_temp_bytes(int64_t n) { return radix_sort_temp_bytes(n); }
 
 static int bits_for(uint64_t v) {
   int b = 1;
@@ -181,9 +173,7 @@ hipError_t cells_build(const double* x, const double* y, const double* g1, const
                        int32_t* inv, hipStream_t s) {
   const int64_t ncells = (int64_t)g.ncx * g.ncy;
   hipLaunchKernelGGL(key_kernel, dim3(grid1d(n)), dim3(256), 0, s, x, y, n, g, key_a, idx_a);
-  size_t tb = sort_tmp_bytes;
-  hipError_t e = hipcub::DeviceRadixSort::SortPairs(sort_tmp, tb, key_a, key_b, idx_a, idx_b, (int)n,
-                                                    0, bits_for((uint64_t)ncells), s);
+  hipError_t e = radix_sort_pairs(sort_tmp, sort_tmp_bytes, key_a, key_b, idx_a, idx_b, n, bits_for((uint64_t)ncells), s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(starts_kernel, dim3(grid1d(n + 1)), dim3(256), 0, s, key_b, n, ncells, cell_start);
   if (fp64)
@@ -195,13 +185,16 @@ hipError_t cells_build(const double* x, const double* y, const double* g1, const
   return hipGetLastError();
 }
 
-// Morton-ordered list of all sorted positions (uses key_b from cells_build).
+// Morton-ordered list of all sorted positions (uses key_b from cells_build;
+// mkey_a and idx_a are overwritten).
 hipError_t cells_centre_order(const uint32_t* skey, int64_t n, const Grid& g, uint32_t* mkey_a,
                               uint32_t* mkey_b, int32_t* idx_a, int32_t* out, void* sort_tmp,
                               size_t sort_tmp_bytes, hipStream_t s) {
   hipLaunchKernelGGL(morton_kernel, dim3(grid1d(n)), dim3(256), 0, s, skey, n, g.ncx, mkey_a, idx_a);
-  size_t tb = sort_tmp_bytes;
-  return hipcub::DeviceRadixSort::SortPairs(sort_tmp, tb, mkey_a, mkey_b, idx_a, out, (int)n, 0, 32, s);
+  // cell coordinates below 2^b interleave into keys below 2^(2b); spread16
+  // keeps 16 bits of each coordinate
+  const int b = bits_for((uint64_t)std::max(g.ncx, g.ncy));
+  return radix_sort_pairs(sort_tmp, sort_tmp_bytes, mkey_a, mkey_b, idx_a, out, n, b > 16 ? 32 : 2 * b, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -329,12 +322,7 @@ struct RedLayout {
 RedLayout red_layout(int64_t n) {
   const int64_t nn = n > 0 ? n : 1;
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
-  size_t t64 = 0, t32 = 0, tsc = 0;
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, t64, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                           (const int32_t*)nullptr, (int32_t*)nullptr, (int)nn, 0, 64);
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, t32, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                           (const int32_t*)nullptr, (int32_t*)nullptr, (int)nn, 0, 32);
-  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tsc, (const int32_t*)nullptr, (int32_t*)nullptr, (int)nn);
+  const size_t tsort = radix_sort_temp_bytes(nn), tsc = scan_temp_bytes(nn);
   RedLayout L{};
   size_t o = 0;
   auto take = [&](size_t b) { size_t r = o; o += up(b); return r; };
@@ -350,7 +338,7 @@ RedLayout red_layout(int64_t n) {
   L.kb = take(nn * 4);
   L.pa = take(nn * 4);
   L.pb = take(nn * 4);
-  L.tmp_bytes = std::max(t64, std::max(t32, tsc)) + 4096;
+  L.tmp_bytes = std::max(tsort, tsc);
   L.tmp = take(L.tmp_bytes);
   L.total = o;
   return L;
@@ -385,14 +373,12 @@ hipError_t reduced_build(const double* x, const double* y, const double* g1, con
   const int64_t ny = (int64_t)floor((ymax - y0) / delta) + 1;
   if (nx <= 0 || ny <= 0 || (double)nx * (double)ny >= 1.8e19) return hipErrorInvalidValue;
   hipLaunchKernelGGL(rkey_kernel, dim3(grid1d(n)), dim3(256), 0, s, x, y, n, x0, y0, delta, nx, ny, k64a, ia);
-  size_t tb = L.tmp_bytes;
   int kbits = 1;
   while (kbits < 64 && (1ull << kbits) <= (uint64_t)nx * (uint64_t)ny) ++kbits;
-  hipError_t e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, k64a, k64b, ia, ib, (int)n, 0, kbits, s);
+  hipError_t e = radix_sort_pairs(tmp, L.tmp_bytes, k64a, k64b, ia, ib, n, kbits, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(rhead_kernel, dim3(grid1d(n)), dim3(256), 0, s, k64b, n, head);
-  tb = L.tmp_bytes;
-  e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, head, segid, (int)n, s);
+  e = exclusive_scan_i32(tmp, L.tmp_bytes, head, segid, n, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(rsegstart_kernel, dim3(grid1d(n)), dim3(256), 0, s, head, segid, n, segstart);
   hipLaunchKernelGGL(rsum_kernel, dim3(grid1d(n)), dim3(256), 0, s, x, y, g1, g2, w, ib, head, segid,
@@ -406,8 +392,7 @@ hipError_t reduced_build(const double* x, const double* y, const double* g1, con
   // search-grid order of the pseudo-galaxies, cell starts, records
   const int64_t ncells = (int64_t)g.ncx * g.ncy;
   hipLaunchKernelGGL(key_kernel, dim3(grid1d(m)), dim3(256), 0, s, pd, pd + n, m, g, ka, pa);
-  tb = L.tmp_bytes;
-  e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, ka, kb, pa, pb, (int)m, 0, bits_for((uint64_t)ncells), s);
+  e = radix_sort_pairs(tmp, L.tmp_bytes, ka, kb, pa, pb, m, bits_for((uint64_t)ncells), s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(starts_kernel, dim3(grid1d(m + 1)), dim3(256), 0, s, kb, m, ncells, cell_start);
   hipLaunchKernelGGL(rgather_kernel, dim3(grid1d(m)), dim3(256), 0, s, pd, n, pb, m,

@@ -149,6 +149,21 @@ struct StageAArgs {
   const int32_t* rcell[TREE_LEVELS_MAX];     // their cell starts
 };
 
+// Stable radix sort of (key, value) pairs on the low `bits` bits of the keys
+// (every key must be below 2^bits), 1 <= bits <= 8 sizeof(K), n < 2^31.
+// Sorted pairs in key_b / val_b; key_a / val_a are overwritten.  tmp holds at
+// least radix_sort_temp_bytes(n) bytes.  Instantiated for uint32_t and
+// uint64_t keys.
+size_t radix_sort_temp_bytes(int64_t n);
+template <typename K>
+hipError_t radix_sort_pairs(void* tmp, size_t tmp_bytes, K* key_a, K* key_b, int32_t* val_a, int32_t* val_b,
+                            int64_t n, int bits, hipStream_t s);
+// out[i] = in[0] + ... + in[i-1] (int32, n < 2^31; in and out may not
+// overlap); tmp holds at least scan_temp_bytes(n) bytes.
+size_t scan_temp_bytes(int64_t n);
+hipError_t exclusive_scan_i32(void* tmp, size_t tmp_bytes, const int32_t* in, int32_t* out, int64_t n,
+                              hipStream_t s);
+
 // Reduced catalogue of cell side delta anchored at (x0, y0) (tree
 // approximation): pseudo-galaxies sorted on the search grid g, with cell
 // starts.  Scratch is caller-provided (reduced_scratch_bytes); returns the

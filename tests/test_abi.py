@@ -228,3 +228,26 @@ def test_basetree_rejects_centre_subsets_and_fp64():
         fp.estimate_3pcf_multipoles(x, x, x * 0, x * 0, x * 0 + 1, [1.0, 2.0, 4.0], 2,
                                     precision="fp16", base=(0.5, 9, 4.0))
     assert ei.value.status == -1
+
+
+def test_debug_sort_rejects_bad_arguments():
+    """The sort check export validates on the host before any device work."""
+    from paper_2509_07974_amd import _lib
+    lib = ensure_built()
+    k = np.array([1, 2, 40], dtype=np.uint64)
+    v = np.zeros(3, np.int32)
+    ko = np.zeros(3, np.uint64)
+    vo = np.zeros(3, np.int32)
+
+    def call(n, bits, kbytes, keys=k.ctypes.data, outk=ko.ctypes.data):
+        return lib.fpcf4_debug_sort_pairs(keys, v.ctypes.data, n, bits, kbytes, outk, vo.ctypes.data)
+
+    assert call(3, 5, 8) == _lib.E_INVALID_ARG      # 40 is not below 2^5
+    assert call(3, 33, 4) == _lib.E_INVALID_ARG     # 32-bit keys take at most 32 bits
+    assert call(3, 0, 8) == _lib.E_INVALID_ARG
+    assert call(3, 65, 8) == _lib.E_INVALID_ARG
+    assert call(3, 6, 2) == _lib.E_INVALID_ARG
+    assert call(-1, 6, 8) == _lib.E_INVALID_ARG
+    assert call(3, 6, 8, keys=None) == _lib.E_INVALID_ARG
+    assert call(3, 6, 8, outk=None) == _lib.E_INVALID_ARG
+    assert call(0, 6, 8) == _lib.OK                 # nothing to sort: no device work
