@@ -163,7 +163,7 @@ fpcf4_status make_plan(const fpcf4_catalogue* cat, const fpcf4_bins* bins,
   if (tile <= 0) tile = (int64_t)(kTileRecordBudget / rec_per_centre);
   if (tile > P.ncent) tile = P.ncent;
   if (tile < 1) tile = 1;
-  if (tile > (int64_t(1) << 29)) tile = int64_t(1) << 29;   // 4 work-items per centre in the relayout grid < 2^32
+  if (tile > (int64_t(1) << 28)) tile = int64_t(1) << 28;   // <= 8 work-items per centre along x of the relayout grid
   P.tile = tile;
   P.ldc = (tile + 15) / 16 * 16;
   P.ntiles = P.ncent > 0 ? (P.ncent + tile - 1) / tile : 0;
