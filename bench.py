@@ -443,7 +443,7 @@ def main():
                     help="only run one plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU path "
+        print(json.dumps({"error": "the library runs on one GPU only; the multi-GPU path "
                           "(centre sharding + one all-reduce of Upsilon) is not built"}))
         sys.exit(2)
 
