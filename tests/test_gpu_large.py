@@ -59,3 +59,19 @@ def test_lognormal10m_tiles_match_single_tile(fp):
     many = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp64", centers=idx,
                                        tile_centers=777)
     assert np.all(rel_per_mu(many, one) < 1e-13)
+
+
+@pytest.mark.timeout(600)
+def test_lognormal10m_tree_sampled_centres(fp):
+    """The tree approximation at the largest workload (reduced catalogues on
+    0.5', 1', 2' grids, r_min 40: the six outer bins from reduced
+    catalogues, two of them on each grid; nmax 15): four seeded centres
+    against the tree oracle."""
+    cat, edges, nmax, _ = c4()
+    tree = (0.5, 3, 40.0)
+    assert oracle.tree_levels(edges, *tree) == [0] * 10 + [1, 1, 2, 2, 3, 3]
+    idx = np.sort(np.random.default_rng(17).choice(cat.n, 4, replace=False))
+    print(f"tree lognormal-10m centres {idx.tolist()}", flush=True)
+    got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp16", tree=tree, centers=idx)
+    ref = oracle.upsilon_tree(*cat.arrays(), edges, nmax, *tree, centers=idx)
+    assert_parity(got, ref, "fp16", label="tree lognormal-10m")
