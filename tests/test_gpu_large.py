@@ -75,3 +75,23 @@ def test_lognormal10m_tree_sampled_centres(fp):
     got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp16", tree=tree, centers=idx)
     ref = oracle.upsilon_tree(*cat.arrays(), edges, nmax, *tree, centers=idx)
     assert_parity(got, ref, "fp16", label="tree lognormal-10m")
+
+
+@functools.lru_cache(None)
+def c4_sample3(m=30):
+    cat, edges, _, _ = c4()
+    idx = np.sort(np.random.default_rng(19).choice(cat.n, 8, replace=False))
+    return idx, oracle.upsilon3(*cat.arrays(), edges, m, centers=idx), \
+        oracle.abs_bound(*cat.arrays(), edges, idx, order=3)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", ["fp16", "fp64"])
+def test_lognormal10m_3pcf_sampled_centres(fp, prec):
+    """The shear 3PCF at the largest workload, multipoles |n| <= 30 (records
+    of order 15), eight seeded centres with every galaxy as neighbour."""
+    cat, edges, _, _ = c4()
+    idx, ref, S = c4_sample3()
+    print(f"3pcf lognormal-10m m=30 centres {idx.tolist()} {prec}", flush=True)
+    got = fp.estimate_3pcf_multipoles(*cat.arrays(), edges, 30, precision=prec, centers=idx)
+    assert_parity(got, ref, prec, S, nbin=2, label="3pcf lognormal-10m")
