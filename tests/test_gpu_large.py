@@ -61,20 +61,29 @@ def test_lognormal10m_tiles_match_single_tile(fp):
     assert np.all(rel_per_mu(many, one) < 1e-13)
 
 
+C4_TREE = (0.5, 3, 40.0)   # grids of 0.5', 1', 2', r_min 40
+
+
+@functools.lru_cache(None)
+def c4_tree_sample():
+    cat, edges, nmax, _ = c4()
+    idx = np.sort(np.random.default_rng(17).choice(cat.n, 4, replace=False))
+    return idx, oracle.upsilon_tree(*cat.arrays(), edges, nmax, *C4_TREE, centers=idx)
+
+
 @pytest.mark.timeout(600)
-def test_lognormal10m_tree_sampled_centres(fp):
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_lognormal10m_tree_sampled_centres(fp, prec):
     """The tree approximation at the largest workload (reduced catalogues on
     0.5', 1', 2' grids, r_min 40: the six outer bins from reduced
     catalogues, two of them on each grid; nmax 15): four seeded centres
     against the tree oracle."""
     cat, edges, nmax, _ = c4()
-    tree = (0.5, 3, 40.0)
-    assert oracle.tree_levels(edges, *tree) == [0] * 10 + [1, 1, 2, 2, 3, 3]
-    idx = np.sort(np.random.default_rng(17).choice(cat.n, 4, replace=False))
-    print(f"tree lognormal-10m centres {idx.tolist()}", flush=True)
-    got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision="fp16", tree=tree, centers=idx)
-    ref = oracle.upsilon_tree(*cat.arrays(), edges, nmax, *tree, centers=idx)
-    assert_parity(got, ref, "fp16", label="tree lognormal-10m")
+    assert oracle.tree_levels(edges, *C4_TREE) == [0] * 10 + [1, 1, 2, 2, 3, 3]
+    idx, ref = c4_tree_sample()
+    print(f"tree lognormal-10m centres {idx.tolist()} {prec}", flush=True)
+    got = fp.estimate_4pcf_multipoles(*cat.arrays(), edges, nmax, precision=prec, tree=C4_TREE, centers=idx)
+    assert_parity(got, ref, prec, label="tree lognormal-10m")
 
 
 @functools.lru_cache(None)
@@ -89,7 +98,8 @@ def c4_sample3(m=30):
 @pytest.mark.parametrize("prec", ["fp16", "fp64"])
 def test_lognormal10m_3pcf_sampled_centres(fp, prec):
     """The shear 3PCF at the largest workload, multipoles |n| <= 30 (records
-    of order 15), eight seeded centres with every galaxy as neighbour."""
+    of order 15), eight seeded centres with every galaxy as neighbour (both
+    mixed precisions take the same binary32 records here)."""
     cat, edges, _, _ = c4()
     idx, ref, S = c4_sample3()
     print(f"3pcf lognormal-10m m=30 centres {idx.tolist()} {prec}", flush=True)
